@@ -1,0 +1,222 @@
+/*
+ * tof.h -- C ABI of the MI355X (gfx950) gradient engine for finite-difference
+ * topology optimization of permanent magnets (Abert et al. 2017).
+ *
+ * One gradient evaluation takes a density field rho on a regular cuboid-cell
+ * grid to
+ *   M = chi rho^p M0                       (Sec. Methodology, penalized magnetization)
+ *   H = -N (*) M                           (Sec. Discretization, eq. (convolution);
+ *                                           N the positive Newell tensor, eq. (demag_tensor))
+ *   J(H), g = dJ/dH                        (eq. (objective_function))
+ *   A = -N (*) g                           (the same operator, Sec. Methodology: the
+ *                                           adjoint problem is a stray-field problem)
+ *   dJ/drho = chi p rho^(p-1) M0 . A       (eqs. (dj_drho), (adjoint1); the paper
+ *                                           prints a minus sign, the discrete chain
+ *                                           rule gives this plus sign)
+ * The convolution runs as a zero-padded FFT convolution (padded lengths
+ * L >= 2n - 1 per axis, default 2n), as Sec. Discretization prescribes.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are C order [nz][ny][nx] (x fastest); vector fields are
+ *    component-major [3][nz][ny][nx] (or [c][...] with c listed components).
+ *  - Pointers named *_host are host memory; every other array pointer is
+ *    device memory owned by the caller, of the context's dtype (float for
+ *    TOF_F32, double for TOF_F64) unless stated otherwise.  J is always a
+ *    device double.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Hot
+ *    calls only enqueue work on it and return without synchronizing, and
+ *    allocate nothing; results are valid once the stream has reached them.
+ *  - Every call validates its arguments before any launch and returns a
+ *    tof_status; TOF_OK is 0.  On failure tof_last_error(ctx) describes it
+ *    (a thread-local message for calls that have no context).  No exception
+ *    crosses the ABI.
+ *  - A context is not thread-safe; calls that overlap on one context race.
+ *    Use one context per stream.
+ */
+#ifndef TOF_H
+#define TOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tof_ctx tof_ctx;
+
+typedef enum {
+    TOF_OK = 0,
+    TOF_ERR_INVALID = -1,      /* bad argument (null pointer, bad box, size) */
+    TOF_ERR_UNSUPPORTED = -2,  /* valid but not implemented (e.g. padded length with a prime > 7) */
+    TOF_ERR_OOM = -3,          /* device allocation failed */
+    TOF_ERR_HIP = -4,          /* a HIP runtime call failed */
+    TOF_ERR_NUMERIC = -5,      /* a setup self-check failed */
+    TOF_ERR_STATE = -6         /* call order: design/objective not set */
+} tof_status;
+
+typedef enum { TOF_F32 = 1, TOF_F64 = 2 } tof_dtype;
+
+/* Objective kinds (S = number of sensor cells, t = target, lam = weight). */
+typedef enum {
+    TOF_J_MEAN_SQ_HZ = 1,        /* J = (1/S) sum_s (Hz_s - t)^2 */
+    TOF_J_MEAN_SQ_HZ_GRADXY = 2, /* J = (1/S) sum_s (Hz_s - t)^2 + lam (1/S) sum_s (DxHz_s^2 + DyHz_s^2),
+                                    central differences with the cell sizes; the sensor needs
+                                    in-grid x and y neighbours */
+    TOF_J_MEAN_SQ_H_TARGET = 3,  /* J = (1/S) sum_s |H_s - H*_s|^2, H* given per sensor cell */
+    TOF_J_NEG_HALF_HZ2 = 4       /* J = -1/2 V_cell sum_s Hz_s^2 (the paper's benchmark objective,
+                                    Sec. "Validation and Benchmarks") */
+} tof_objective_kind;
+
+/* Grid: the FFT box of nx*ny*nz cells of size dx*dy*dz.  Lx, Ly, Lz are the
+ * padded FFT lengths; 0 selects 2n, or, when 2n has a prime factor above 7,
+ * the smallest even 7-smooth length above 2n.  Explicit lengths must be even,
+ * 7-smooth, >= 2n - 1 and <= 1024 (so n <= 512 per axis). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+    int32_t Lx, Ly, Lz;
+    int32_t dtype;          /* tof_dtype */
+} tof_grid;
+
+/* Half-open cell index box [x0,x1) x [y0,y1) x [z0,z1). */
+typedef struct {
+    int32_t x0, x1, y0, y1, z0, z1;
+} tof_box;
+
+typedef struct {
+    int32_t kind;               /* tof_objective_kind */
+    tof_box sensor;             /* sensor cells */
+    double target;              /* t (kinds 1, 2) */
+    double lambda_grad;         /* lam (kind 2) */
+    const double *h_target_host;/* kind 3: H* as [3][sensor cells], C order over the sensor box; else NULL */
+} tof_objective;
+
+/*
+ * tof_create -- validate the grid, pick FFT plans, allocate the workspaces
+ * and compute the tensor spectra (setup; allowed to allocate and to block).
+ * The demagnetization tensor (eq. (demag_tensor)) is evaluated on the GPU
+ * from Newell's closed form in double-double arithmetic, wrapped onto the
+ * padded box and transformed in FP64; the spectra are stored in the grid's
+ * dtype.  On success *out owns all device memory of the context.
+ * Errors: TOF_ERR_INVALID (null/empty/oversized grid, non-positive cell),
+ * TOF_ERR_UNSUPPORTED (explicit L not 7-smooth or too small), TOF_ERR_OOM,
+ * TOF_ERR_HIP, TOF_ERR_NUMERIC (tensor spectra not real to 1e-9 relative).
+ */
+tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out);
+
+/* Release everything the context owns.  NULL is a no-op. */
+void tof_destroy(tof_ctx *ctx);
+
+/*
+ * tof_set_design -- the design region chi and magnetization M = chi rho^p M0.
+ *  design:   index box of design cells (NULL = whole grid).
+ *  mask:     optional device uint8 [nz][ny][nx]; chi = box && mask != 0.
+ *  m0_host:  uniform M0 (3 doubles); ignored when m0_field is given.
+ *  m0_field: optional device [3][nz][ny][nx] of the dtype: spatially varying M0.
+ *  p:        penalization exponent, 1 <= p <= 16 (integer; rho^p by multiplication).
+ * Pointers are borrowed: mask and m0_field must stay valid while used.
+ * Errors: TOF_ERR_INVALID.
+ */
+tof_status tof_set_design(tof_ctx *ctx, const tof_box *design, const uint8_t *mask,
+                          const double m0_host[3], const void *m0_field, int32_t p);
+
+/*
+ * tof_set_objective -- the objective J and its sensor cells.  Copies
+ * h_target_host to the device.  Errors: TOF_ERR_INVALID (box outside the
+ * grid, missing x/y neighbours for kind 2, missing H* for kind 3).
+ */
+tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj);
+
+/*
+ * tof_field -- H = -N (*) (chi rho^p M0) on the whole grid.
+ *  rho:        device [nz][ny][nx].
+ *  H:          device [c][nz][ny][nx], c = number of bits in comps_mask
+ *              (bit 0 = Hx, bit 1 = Hy, bit 2 = Hz), in component order.
+ * Errors: TOF_ERR_INVALID, TOF_ERR_STATE (no design), TOF_ERR_HIP.
+ */
+tof_status tof_field(tof_ctx *ctx, const void *rho, void *H, int32_t comps_mask, void *stream);
+
+/*
+ * tof_objective_and_grad -- one gradient evaluation: forward field on the
+ * cells J reads, J (FP64, fixed-order reduction), g = dJ/dH, the adjoint
+ * field A = -N (*) g on the design cells, dJ/drho = chi p rho^(p-1) M0 . A.
+ *  rho:  device [nz][ny][nx].
+ *  J:    device double[1] (may be NULL).
+ *  grad: device [nz][ny][nx]; zero outside the design region.
+ * Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_HIP.
+ */
+tof_status tof_objective_and_grad(tof_ctx *ctx, const void *rho, double *J, void *grad,
+                                  void *stream);
+
+/*
+ * tof_adjoint -- vector-Jacobian product of tof_field: given any gH =
+ * dL/dH as device [3][nz][ny][nx], writes dL/drho = chi p rho^(p-1) M0 .
+ * (-N (*) gH) to grad [nz][ny][nx] (zero outside the design region).
+ * Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_HIP.
+ */
+tof_status tof_adjoint(tof_ctx *ctx, const void *rho, const void *gH, void *grad, void *stream);
+
+/*
+ * tof_project_step -- one projected-gradient update on the design cells,
+ * rho <- clamp(rho - alpha grad / max|grad|, 0, 1); cells outside the design
+ * region are left unchanged; a zero gradient leaves rho unchanged.
+ * rho, grad: device [nz][ny][nx].  Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_HIP.
+ */
+tof_status tof_project_step(tof_ctx *ctx, void *rho, const void *grad, double alpha, void *stream);
+
+/*
+ * tof_tensor -- the real-space tensor as computed on the GPU (for checks):
+ * N_c(k) for offsets 0 <= k_a < n_a, device double [6][nz][ny][nx],
+ * components xx, yy, zz, xy, xz, yz; other offsets follow by parity (the
+ * diagonal is even in every axis, xy odd in x and y, xz odd in x and z, yz odd
+ * in y and z).  Allocates temporaries (setup-class call) and synchronizes.
+ * Errors: TOF_ERR_INVALID, TOF_ERR_OOM, TOF_ERR_HIP.
+ */
+tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream);
+
+/*
+ * Per-launch timing (a measurement aid).  While enabled, every hot call
+ * brackets each kernel launch with HIP events on its launch stream.  Slots:
+ * 0-4 the passes of the forward convolution (x, y, z with the tensor product,
+ * inverse y, inverse x with its epilogue), 5 the objective, 6-10 the passes of
+ * the adjoint convolution, 11 the zero fill of the gradient outside the design
+ * region.  At most 1024 calls are recorded between reads; later ones are not
+ * timed.  Errors: TOF_ERR_INVALID, TOF_ERR_HIP.
+ */
+#define TOF_PROFILE_SLOTS 12
+tof_status tof_profile_enable(tof_ctx *ctx, int32_t enable);
+
+/*
+ * Synchronizes the recorded events, then per slot writes the summed
+ * milliseconds, the number of timed launches and the algorithmic bytes of one
+ * launch (the arrays the pass must read and write: its input and output, the
+ * density it reads, the tensor spectrum octant it reads), then clears the
+ * record.  Host arrays of TOF_PROFILE_SLOTS entries.  Errors: TOF_ERR_INVALID,
+ * TOF_ERR_HIP.
+ */
+tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[], double bytes_host[]);
+
+/* Padded lengths chosen for the context: out[0..2] = Lx, Ly, Lz. */
+tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3]);
+
+/* Device bytes the context holds (workspaces and spectra). */
+size_t tof_workspace_bytes(const tof_ctx *ctx);
+
+/* Last error message of the context (or of this thread when ctx is NULL). */
+const char *tof_last_error(const tof_ctx *ctx);
+
+/*
+ * tof_dd_newell_host -- the double-double Newell evaluation the GPU setup
+ * uses, run on the host (same source), for CPU-side checks: the tensor entry
+ * of component c (0..5 as above) at offset (kx, ky, kz) >= 0 for cell size
+ * (dx, dy, dz), rounded to double.  Returns NaN for bad arguments.
+ */
+double tof_dd_newell_host(int32_t c, int32_t kx, int32_t ky, int32_t kz,
+                          double dx, double dy, double dz);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOF_H */

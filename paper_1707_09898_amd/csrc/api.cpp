@@ -1,0 +1,751 @@
+// C-ABI host side of the gradient engine: argument validation, FFT plans,
+// workspace ownership, the GPU tensor setup and the order of the passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tof.h"
+#include "dd.h"
+#include "engine.h"
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr int kMaxL = 1024;
+
+struct Plan1D {
+    int L = 0;
+    std::vector<int> radix;
+    void *tw_f = nullptr;   // cplx<float>[L]
+    void *tw_d = nullptr;   // cplx<double>[L]
+    FftPlanDev dev(bool f64) const
+    {
+        FftPlanDev p{};
+        p.L = L;
+        p.nst = (int)radix.size();
+        for (size_t i = 0; i < radix.size(); ++i) p.radix[i] = radix[i];
+        p.tw = f64 ? tw_d : tw_f;
+        return p;
+    }
+};
+
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct tof_ctx {
+    int nx = 0, ny = 0, nz = 0;
+    double dx = 1, dy = 1, dz = 1;
+    int Lx = 0, Ly = 0, Lz = 0, hx = 0;
+    bool f64 = false;
+    size_t wsize = 4;   // bytes per real
+    Plan1D px, py, pz;
+    // spectra [6][hx][hkz][ky_pitch] of the working precision
+    DeviceBuf spec;
+    int hkz = 0, ky_pitch = 0;
+    long long comp_stride = 0;
+    // pass workspaces
+    DeviceBuf A, B, C;
+    int Zrows = 0;
+    // objective buffers
+    DeviceBuf Hs, G, Ht;
+    DeviceBuf scratch64;
+    // design
+    bool has_design = false;
+    Box design{};
+    const uint8_t *mask = nullptr;
+    double m0[3] = {0, 0, 1};
+    const void *m0f = nullptr;
+    int p = 3;
+    // objective
+    bool has_obj = false;
+    int kind = 0;
+    Box sensor{}, ob{};
+    double target = 0, lam = 0;
+    // per-launch timing
+    bool prof_on = false;
+    int prof_calls[TOF_PROFILE_SLOTS] = {};
+    std::vector<hipEvent_t> prof_ev;   // [slot][call][2]
+    double prof_bytes[TOF_PROFILE_SLOTS] = {};
+    std::string err;
+};
+
+namespace {
+
+constexpr int kProfCalls = 1024;
+
+tof_status fail(tof_ctx *ctx, tof_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    g_thread_error = msg;
+    return st;
+}
+
+tof_status hip_fail(tof_ctx *ctx, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? TOF_ERR_OOM : TOF_ERR_HIP, m);
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+// Launch through `fn` and, when timing is on, bracket it with events of the
+// slot on the same stream; `bytes` is the pass's algorithmic traffic.
+template <typename F>
+hipError_t timed(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn)
+{
+    if (!ctx->prof_on || ctx->prof_calls[slot] >= kProfCalls) return fn();
+    hipEvent_t *ev = &ctx->prof_ev[((size_t)slot * kProfCalls + ctx->prof_calls[slot]) * 2];
+    hipError_t e = hipEventRecord(ev[0], st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev[1], st);
+    if (e != hipSuccess) return e;
+    ctx->prof_calls[slot]++;
+    ctx->prof_bytes[slot] = bytes;
+    return hipSuccess;
+}
+
+bool smooth7(int L)
+{
+    if (L < 1) return false;
+    for (int f : {2, 3, 5, 7})
+        while (L % f == 0) L /= f;
+    return L == 1;
+}
+
+// 2n when it is 7-smooth, else the smallest even 7-smooth length >= 2n - 1
+// (the real-to-complex pass along x needs an even length; the other axes
+// use the same rule for simplicity).
+int choose_length(int n)
+{
+    int L = 2 * n;
+    while (!smooth7(L)) L += 2;
+    return L;
+}
+
+std::vector<int> factor_radices(int L)
+{
+    std::vector<int> r;
+    while (L % 8 == 0) { r.push_back(8); L /= 8; }
+    while (L % 4 == 0) { r.push_back(4); L /= 4; }
+    while (L % 2 == 0) { r.push_back(2); L /= 2; }
+    for (int f : {3, 5, 7})
+        while (L % f == 0) { r.push_back(f); L /= f; }
+    return r;
+}
+
+tof_status dev_alloc(tof_ctx *ctx, DeviceBuf &b, size_t bytes)
+{
+    if (b.p && b.bytes >= bytes) return TOF_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) return TOF_OK;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(ctx, TOF_ERR_OOM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed");
+    }
+    b.bytes = bytes;
+    return TOF_OK;
+}
+
+tof_status make_plan(tof_ctx *ctx, Plan1D &pl, int L)
+{
+    pl.L = L;
+    pl.radix = factor_radices(L);
+    if ((int)pl.radix.size() > TOF_MAX_STAGES)
+        return fail(ctx, TOF_ERR_UNSUPPORTED, "too many FFT stages");
+    std::vector<float> tf(2 * L);
+    std::vector<double> td(2 * L);
+    for (int k = 0; k < L; ++k) {
+        // w_L^k = exp(-2 pi i k / L) in extended precision, rounded once
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)L;
+        const long double c = cosl(a), s = -sinl(a);
+        td[2 * k] = (double)c;
+        td[2 * k + 1] = (double)s;
+        tf[2 * k] = (float)c;
+        tf[2 * k + 1] = (float)s;
+    }
+    HIP_TRY(ctx, hipMalloc(&pl.tw_f, sizeof(float) * 2 * L));
+    HIP_TRY(ctx, hipMalloc(&pl.tw_d, sizeof(double) * 2 * L));
+    HIP_TRY(ctx, hipMemcpy(pl.tw_f, tf.data(), sizeof(float) * 2 * L, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(pl.tw_d, td.data(), sizeof(double) * 2 * L, hipMemcpyHostToDevice));
+    return TOF_OK;
+}
+
+bool box_ok(const Box &b, int nx, int ny, int nz)
+{
+    return b.x0 >= 0 && b.x1 <= nx && b.y0 >= 0 && b.y1 <= ny && b.z0 >= 0 && b.z1 <= nz && b.x0 < b.x1 &&
+           b.y0 < b.y1 && b.z0 < b.z1;
+}
+
+Box to_box(const tof_box &b) { return Box{b.x0, b.x1, b.y0, b.y1, b.z0, b.z1}; }
+
+int comp_of(int a, int b)
+{
+    if (a == b) return a;
+    if (a > b) std::swap(a, b);
+    if (a == 0) return b == 1 ? 3 : 4;
+    return 5;
+}
+
+void finish_product(ProductDev &pr)
+{
+    pr.need = 0;
+    for (int o = 0; o < pr.c_out; ++o)
+        for (int i = 0; i < pr.c_in; ++i)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    if (pr.U[o][a] != 0.0 && pr.V[b][i] != 0.0) pr.need |= 1 << comp_of(a, b);
+}
+
+// ---- one convolution: five passes ----
+// slot0 = 0 for the forward convolution, 6 for the adjoint one.
+template <typename R>
+tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const DesignDev<R> &dsg,
+                    View4<const R> src, Box S, Box T, const ProductDev &prod, bool grad_epi, View4<R> out,
+                    const R *m0u, R *grad)
+{
+    const bool f64 = sizeof(R) == 8;
+    const FftPlanDev plx = ctx->px.dev(f64), ply = ctx->py.dev(f64), plz = ctx->pz.dev(f64);
+    cplx<R> *A = (cplx<R> *)ctx->A.p, *B = (cplx<R> *)ctx->B.p, *C = (cplx<R> *)ctx->C.p;
+    const int hx = ctx->hx, Ly = ctx->Ly, Zr = ctx->Zrows;
+    SpectrumDev<R> sp{(const R *)ctx->spec.p, ctx->comp_stride, ctx->hkz, ctx->ky_pitch};
+    // algorithmic bytes of each pass
+    const double w = sizeof(R), cw = 2.0 * sizeof(R);
+    const double nS = (double)S.nx() * S.ny() * S.nz();
+    const double src_bytes = mode == SRC_ARRAY ? prod.c_in * nS * w
+                                               : nS * w * (mode == SRC_RHO_VECTOR ? 4.0 : 1.0);
+    const double a_elems = (double)prod.c_in * hx * S.nz() * S.ny();
+    const double b_in = (double)prod.c_in * hx * S.nz() * Ly;
+    const double b_out = (double)prod.c_out * hx * T.nz() * Ly;
+    const double c_elems = (double)prod.c_out * hx * T.nz() * T.ny();
+    int ncomp = 0;
+    for (int c = 0; c < 6; ++c) ncomp += prod.need >> c & 1;
+    const double spec_bytes = ncomp * (double)hx * ctx->hkz * (Ly / 2 + 1) * w;
+    const double nTrow = (double)T.ny() * T.nz();
+    const double x_out = grad_epi ? nTrow * ctx->nx * w * (2.0 + (dsg.m0f ? 3.0 : 0.0))
+                                  : prod.c_out * nTrow * T.nx() * w;
+    HIP_TRY(ctx, timed(ctx, st, slot0 + 0, src_bytes + a_elems * cw, [&] {
+        return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx);
+    }));
+    HIP_TRY(ctx, timed(ctx, st, slot0 + 1, (a_elems + b_in) * cw, [&] {
+        return launch_line_fft<R>(st, A, B, prod.c_in * hx * S.nz(), S.nz(), (long long)S.nz() * S.ny(), S.ny(),
+                                  (long long)Zr * Ly, Ly, S.y0, S.ny(), 0, Ly, ply, false);
+    }));
+    HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + spec_bytes, [&] {
+        return launch_z_pass<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), sp, prod, false, plz);
+    }));
+    HIP_TRY(ctx, timed(ctx, st, slot0 + 3, (b_out + c_elems) * cw, [&] {
+        return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)Zr * Ly, Ly,
+                                  (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true);
+    }));
+    HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
+        return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad);
+    }));
+    return TOF_OK;
+}
+
+template <typename R>
+DesignDev<R> design_dev(const tof_ctx *ctx, const void *rho)
+{
+    DesignDev<R> d{};
+    d.rho = (const R *)rho;
+    d.mask = ctx->mask;
+    d.m0f = (const R *)ctx->m0f;
+    d.design = ctx->design;
+    d.p = ctx->p;
+    d.nx = ctx->nx;
+    d.ny = ctx->ny;
+    d.nz = ctx->nz;
+    return d;
+}
+
+// Forward product: source chi rho^p (uniform M0 folded in via V) or
+// chi rho^p M0_c (three components); outputs the components in comps_mask.
+ProductDev forward_product(const tof_ctx *ctx, int comps_mask)
+{
+    ProductDev pr{};
+    std::memset(&pr, 0, sizeof(pr));
+    if (ctx->m0f) {
+        pr.c_in = 3;
+        for (int b = 0; b < 3; ++b) pr.V[b][b] = 1.0;
+    } else {
+        pr.c_in = 1;
+        for (int b = 0; b < 3; ++b) pr.V[b][0] = ctx->m0[b];
+    }
+    int o = 0;
+    for (int a = 0; a < 3; ++a)
+        if (comps_mask >> a & 1) pr.U[o++][a] = 1.0;
+    pr.c_out = o;
+    finish_product(pr);
+    return pr;
+}
+
+// Adjoint product: source = dJ/dH components in comps_mask; output M0 . A
+// (one component, uniform M0) or A (three components, varying M0).
+ProductDev adjoint_product(const tof_ctx *ctx, int comps_mask)
+{
+    ProductDev pr{};
+    std::memset(&pr, 0, sizeof(pr));
+    int i = 0;
+    for (int b = 0; b < 3; ++b)
+        if (comps_mask >> b & 1) pr.V[b][i++] = 1.0;
+    pr.c_in = i;
+    if (ctx->m0f) {
+        pr.c_out = 3;
+        for (int a = 0; a < 3; ++a) pr.U[a][a] = 1.0;
+    } else {
+        pr.c_out = 1;
+        for (int a = 0; a < 3; ++a) pr.U[0][a] = ctx->m0[a];
+    }
+    finish_product(pr);
+    return pr;
+}
+
+int popcount3(int m) { return (m & 1) + (m >> 1 & 1) + (m >> 2 & 1); }
+
+template <typename R>
+tof_status adjoint_to_grad(tof_ctx *ctx, hipStream_t st, const void *rho, View4<const R> src, Box S,
+                           int comps_mask, void *grad)
+{
+    DesignDev<R> dsg = design_dev<R>(ctx, rho);
+    ProductDev pr = adjoint_product(ctx, comps_mask);
+    const R one[3] = {(R)1, (R)0, (R)0};
+    View4<R> none{};
+    tof_status s = convolve<R>(ctx, st, 6, SRC_ARRAY, dsg, src, S, ctx->design, pr, true, none, one, (R *)grad);
+    if (s != TOF_OK) return s;
+    const Box d = ctx->design;
+    const double zbytes = ((double)ctx->nx * ctx->ny * ctx->nz - (double)ctx->nx * d.ny() * d.nz()) * sizeof(R);
+    HIP_TRY(ctx, timed(ctx, st, 11, zbytes, [&] {
+        return launch_zero_outside<R>(st, (R *)grad, ctx->nx, ctx->ny, ctx->nz, ctx->design);
+    }));
+    return TOF_OK;
+}
+
+template <typename R>
+tof_status run_field(tof_ctx *ctx, hipStream_t st, const void *rho, void *H, int comps_mask)
+{
+    DesignDev<R> dsg = design_dev<R>(ctx, rho);
+    ProductDev pr = forward_product(ctx, comps_mask);
+    const long long n = (long long)ctx->nx * ctx->ny * ctx->nz;
+    View4<R> out{(R *)H, n, (long long)ctx->ny * ctx->nx, ctx->nx, 0, 0, 0};
+    View4<const R> nosrc{};
+    const Box all{0, ctx->nx, 0, ctx->ny, 0, ctx->nz};
+    const R zero3[3] = {0, 0, 0};
+    return convolve<R>(ctx, st, 0, ctx->m0f ? SRC_RHO_VECTOR : SRC_RHO_SCALAR, dsg, nosrc, ctx->design, all, pr,
+                       false, out, zero3, nullptr);
+}
+
+template <typename R>
+tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho, double *J, void *grad)
+{
+    DesignDev<R> dsg = design_dev<R>(ctx, rho);
+    const int jmask = ctx->kind == TOF_J_MEAN_SQ_H_TARGET ? 7 : 4;
+    const int cj = popcount3(jmask);
+    const Box ob = ctx->ob;
+    const long long nob = (long long)ob.nx() * ob.ny() * ob.nz();
+    ProductDev pf = forward_product(ctx, jmask);
+    View4<R> hs{(R *)ctx->Hs.p, nob, (long long)ob.ny() * ob.nx(), ob.nx(), ob.x0, ob.y0, ob.z0};
+    View4<const R> nosrc{};
+    const R zero3[3] = {0, 0, 0};
+    tof_status s = convolve<R>(ctx, st, 0, ctx->m0f ? SRC_RHO_VECTOR : SRC_RHO_SCALAR, dsg, nosrc, ctx->design,
+                               ob, pf, false, hs, zero3, nullptr);
+    if (s != TOF_OK) return s;
+    const double obytes = 2.0 * cj * nob * sizeof(R);
+    HIP_TRY(ctx, timed(ctx, st, 5, obytes, [&] {
+        return launch_objective<R>(st, ctx->kind, (const R *)ctx->Hs.p, ob, ctx->sensor, cj, ctx->target, ctx->lam,
+                                   ctx->dx, ctx->dy, ctx->dx * ctx->dy * ctx->dz, (const double *)ctx->Ht.p, J,
+                                   (R *)ctx->G.p);
+    }));
+    View4<const R> gsrc{(const R *)ctx->G.p, nob, (long long)ob.ny() * ob.nx(), ob.nx(), ob.x0, ob.y0, ob.z0};
+    return adjoint_to_grad<R>(ctx, st, rho, gsrc, ob, jmask, grad);
+}
+
+// ---- tensor setup ----
+tof_status compute_spectra(tof_ctx *ctx, hipStream_t st)
+{
+    const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz;
+    const int Lx = ctx->Lx, Ly = ctx->Ly, Lz = ctx->Lz, hx = ctx->hx;
+    const int lx = nx + 1, ly = ny + 1, lz = nz + 1;
+    DeviceBuf lat, W, A64, B64, bits;
+    struct Guard {
+        DeviceBuf *b[5];
+        ~Guard()
+        {
+            for (DeviceBuf *x : b)
+                if (x->p) (void)hipFree(x->p);
+        }
+    } guard{{&lat, &W, &A64, &B64, &bits}};
+    tof_status s;
+    if ((s = dev_alloc(ctx, lat, sizeof(double) * 2 * (size_t)lx * ly * lz)) != TOF_OK) return s;
+    if ((s = dev_alloc(ctx, W, sizeof(double) * (size_t)Lx * Ly * Lz)) != TOF_OK) return s;
+    if ((s = dev_alloc(ctx, A64, sizeof(cplx<double>) * (size_t)hx * Lz * Ly)) != TOF_OK) return s;
+    if ((s = dev_alloc(ctx, B64, sizeof(cplx<double>) * (size_t)hx * Lz * Ly)) != TOF_OK) return s;
+    if ((s = dev_alloc(ctx, bits, 2 * sizeof(unsigned long long))) != TOF_OK) return s;
+    const FftPlanDev plx = ctx->px.dev(true), ply = ctx->py.dev(true), plz = ctx->pz.dev(true);
+    const double scale = -1.0 / ((double)Lx * Ly * Lz);
+    SpectrumDev<double> nospec{};
+    ProductDev fwd{};
+    std::memset(&fwd, 0, sizeof(fwd));
+    fwd.c_in = fwd.c_out = 1;
+    DesignDev<double> nodsg{};
+    const Box whole{0, Lx, 0, Ly, 0, Lz};
+    View4<const double> wsrc{(const double *)W.p, 0, (long long)Ly * Lx, Lx, 0, 0, 0};
+    unsigned long long *mi = (unsigned long long *)bits.p, *mr = mi + 1;
+    for (int c = 0; c < 6; ++c) {
+        HIP_TRY(ctx, launch_newell_lattice(st, c, lx, ly, lz, ctx->dx, ctx->dy, ctx->dz, (double *)lat.p));
+        HIP_TRY(ctx, hipMemsetAsync(W.p, 0, W.bytes, st));
+        HIP_TRY(ctx, launch_newell_stencil(st, c, nx, ny, nz, lx, ly, ctx->dx, ctx->dy, ctx->dz,
+                                           (const double *)lat.p, (double *)W.p, Lx, Ly, Lz, nullptr));
+        HIP_TRY(ctx, launch_x_forward<double>(st, SRC_ARRAY, nodsg, wsrc, whole, 1, plx, (cplx<double> *)A64.p, hx));
+        HIP_TRY(ctx, launch_line_fft<double>(st, (const cplx<double> *)A64.p, (cplx<double> *)B64.p, hx * Lz, Lz,
+                                             (long long)Lz * Ly, Ly, (long long)Lz * Ly, Ly, 0, Ly, 0, Ly, ply,
+                                             false));
+        HIP_TRY(ctx, launch_z_pass<double>(st, (cplx<double> *)B64.p, hx, Ly, Lz, 0, Lz, 0, Lz, nospec, fwd, true,
+                                           plz));
+        if (ctx->f64)
+            HIP_TRY(ctx, launch_extract_spectrum<double>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, scale,
+                                                         (double *)ctx->spec.p + c * ctx->comp_stride, ctx->hkz,
+                                                         ctx->ky_pitch, mi, mr));
+        else
+            HIP_TRY(ctx, launch_extract_spectrum<float>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, scale,
+                                                        (float *)ctx->spec.p + c * ctx->comp_stride, ctx->hkz,
+                                                        ctx->ky_pitch, mi, mr));
+        unsigned long long hb[2];
+        HIP_TRY(ctx, hipMemcpyAsync(hb, bits.p, sizeof(hb), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        double im, re;
+        std::memcpy(&im, &hb[0], 8);
+        std::memcpy(&re, &hb[1], 8);
+        if (!(im <= 1e-9 * re) && re > 0)
+            return fail(ctx, TOF_ERR_NUMERIC, "tensor spectrum of component " + std::to_string(c) +
+                                                  " is not real (max|imag|/max|real| = " +
+                                                  std::to_string(im / re) + ")");
+    }
+    return TOF_OK;
+}
+
+void release(tof_ctx *ctx)
+{
+    for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
+    ctx->prof_ev.clear();
+    DeviceBuf *bufs[] = {&ctx->spec, &ctx->A, &ctx->B, &ctx->C, &ctx->Hs, &ctx->G, &ctx->Ht, &ctx->scratch64};
+    for (DeviceBuf *b : bufs)
+        if (b->p) {
+            (void)hipFree(b->p);
+            b->p = nullptr;
+        }
+    for (Plan1D *pl : {&ctx->px, &ctx->py, &ctx->pz}) {
+        if (pl->tw_f) (void)hipFree(pl->tw_f);
+        if (pl->tw_d) (void)hipFree(pl->tw_d);
+        pl->tw_f = pl->tw_d = nullptr;
+    }
+}
+
+tof_status check_ready(tof_ctx *ctx, bool need_obj)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (!ctx->has_design) return fail(ctx, TOF_ERR_STATE, "tof_set_design has not been called");
+    if (need_obj && !ctx->has_obj) return fail(ctx, TOF_ERR_STATE, "tof_set_objective has not been called");
+    return TOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
+{
+    if (!out) return fail(nullptr, TOF_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (!grid) return fail(nullptr, TOF_ERR_INVALID, "grid is null");
+    const tof_grid g = *grid;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > kMaxL / 2 || g.ny > kMaxL / 2 || g.nz > kMaxL / 2)
+        return fail(nullptr, TOF_ERR_INVALID, "grid sizes must be in [1, 512]");
+    if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !std::isfinite(g.dx) || !std::isfinite(g.dy) ||
+        !std::isfinite(g.dz))
+        return fail(nullptr, TOF_ERR_INVALID, "cell sizes must be positive and finite");
+    if (g.dtype != TOF_F32 && g.dtype != TOF_F64) return fail(nullptr, TOF_ERR_INVALID, "dtype must be TOF_F32 or TOF_F64");
+    int L[3] = {g.Lx, g.Ly, g.Lz};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (L[a] == 0) L[a] = choose_length(n[a]);
+        if (L[a] < 2 * n[a] - 1 || L[a] > kMaxL || !smooth7(L[a]) || (L[a] & 1))
+            return fail(nullptr, TOF_ERR_UNSUPPORTED,
+                        "padded length must be even, 7-smooth, >= 2n-1 and <= 1024 (axis " + std::to_string(a) + ")");
+    }
+    tof_ctx *ctx = new (std::nothrow) tof_ctx();
+    if (!ctx) return fail(nullptr, TOF_ERR_OOM, "host allocation failed");
+    ctx->nx = g.nx; ctx->ny = g.ny; ctx->nz = g.nz;
+    ctx->dx = g.dx; ctx->dy = g.dy; ctx->dz = g.dz;
+    ctx->Lx = L[0]; ctx->Ly = L[1]; ctx->Lz = L[2];
+    ctx->hx = L[0] / 2 + 1;
+    ctx->f64 = g.dtype == TOF_F64;
+    ctx->wsize = ctx->f64 ? 8 : 4;
+    ctx->design = Box{0, g.nx, 0, g.ny, 0, g.nz};
+    hipStream_t st = (hipStream_t)stream;
+    tof_status s;
+    auto bail = [&](tof_status code) {
+        release(ctx);
+        g_thread_error = ctx->err;
+        delete ctx;
+        return code;
+    };
+    if ((s = make_plan(ctx, ctx->px, L[0])) != TOF_OK) return bail(s);
+    if ((s = make_plan(ctx, ctx->py, L[1])) != TOF_OK) return bail(s);
+    if ((s = make_plan(ctx, ctx->pz, L[2])) != TOF_OK) return bail(s);
+    ctx->hkz = L[2] / 2 + 1;
+    ctx->ky_pitch = ((L[1] / 2 + 1) + 15) / 16 * 16;
+    ctx->comp_stride = (long long)ctx->hx * ctx->hkz * ctx->ky_pitch;
+    if ((s = dev_alloc(ctx, ctx->spec, ctx->wsize * 6 * (size_t)ctx->comp_stride)) != TOF_OK) return bail(s);
+    ctx->Zrows = g.nz;
+    const size_t cw = 2 * ctx->wsize;   // complex bytes
+    if ((s = dev_alloc(ctx, ctx->A, cw * 3 * (size_t)ctx->hx * g.nz * g.ny)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->B, cw * 3 * (size_t)ctx->hx * g.nz * L[1])) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->C, cw * 3 * (size_t)ctx->hx * g.nz * g.ny)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->scratch64, 64)) != TOF_OK) return bail(s);
+    if ((s = compute_spectra(ctx, st)) != TOF_OK) return bail(s);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(hip_fail(ctx, e, "tensor setup"));
+    *out = ctx;
+    return TOF_OK;
+}
+
+void tof_destroy(tof_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    release(ctx);
+    delete ctx;
+}
+
+tof_status tof_set_design(tof_ctx *ctx, const tof_box *design, const uint8_t *mask, const double m0_host[3],
+                          const void *m0_field, int32_t p)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    Box d = design ? to_box(*design) : Box{0, ctx->nx, 0, ctx->ny, 0, ctx->nz};
+    if (!box_ok(d, ctx->nx, ctx->ny, ctx->nz)) return fail(ctx, TOF_ERR_INVALID, "design box outside the grid or empty");
+    if (p < 1 || p > 16) return fail(ctx, TOF_ERR_INVALID, "p must be in [1, 16]");
+    if (!m0_field) {
+        if (!m0_host) return fail(ctx, TOF_ERR_INVALID, "give m0_host or m0_field");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(m0_host[a])) return fail(ctx, TOF_ERR_INVALID, "M0 must be finite");
+        if (m0_host[0] == 0 && m0_host[1] == 0 && m0_host[2] == 0)
+            return fail(ctx, TOF_ERR_INVALID, "M0 must not be zero");
+        for (int a = 0; a < 3; ++a) ctx->m0[a] = m0_host[a];
+    }
+    ctx->design = d;
+    ctx->mask = mask;
+    ctx->m0f = m0_field;
+    ctx->p = p;
+    ctx->has_design = true;
+    return TOF_OK;
+}
+
+tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (!obj) return fail(ctx, TOF_ERR_INVALID, "objective is null");
+    if (obj->kind < 1 || obj->kind > 4) return fail(ctx, TOF_ERR_INVALID, "unknown objective kind");
+    Box sb = to_box(obj->sensor);
+    if (!box_ok(sb, ctx->nx, ctx->ny, ctx->nz)) return fail(ctx, TOF_ERR_INVALID, "sensor box outside the grid or empty");
+    Box ob = sb;
+    if (obj->kind == TOF_J_MEAN_SQ_HZ_GRADXY) {
+        if (sb.x0 < 1 || sb.y0 < 1 || sb.x1 > ctx->nx - 1 || sb.y1 > ctx->ny - 1)
+            return fail(ctx, TOF_ERR_INVALID, "the gradient term needs in-grid x and y neighbours of the sensor");
+        ob = Box{sb.x0 - 1, sb.x1 + 1, sb.y0 - 1, sb.y1 + 1, sb.z0, sb.z1};
+    }
+    if (obj->kind == TOF_J_MEAN_SQ_H_TARGET && !obj->h_target_host)
+        return fail(ctx, TOF_ERR_INVALID, "kind 3 needs h_target_host");
+    if (!std::isfinite(obj->target) || !std::isfinite(obj->lambda_grad))
+        return fail(ctx, TOF_ERR_INVALID, "target and lambda must be finite");
+    const int cj = obj->kind == TOF_J_MEAN_SQ_H_TARGET ? 3 : 1;
+    const size_t nob = (size_t)ob.nx() * ob.ny() * ob.nz();
+    const size_t S = (size_t)sb.nx() * sb.ny() * sb.nz();
+    tof_status s;
+    if ((s = dev_alloc(ctx, ctx->Hs, ctx->wsize * cj * nob)) != TOF_OK) return s;
+    if ((s = dev_alloc(ctx, ctx->G, ctx->wsize * cj * nob)) != TOF_OK) return s;
+    if (obj->kind == TOF_J_MEAN_SQ_H_TARGET) {
+        if ((s = dev_alloc(ctx, ctx->Ht, sizeof(double) * 3 * S)) != TOF_OK) return s;
+        HIP_TRY(ctx, hipMemcpy(ctx->Ht.p, obj->h_target_host, sizeof(double) * 3 * S, hipMemcpyHostToDevice));
+    }
+    ctx->kind = obj->kind;
+    ctx->sensor = sb;
+    ctx->ob = ob;
+    ctx->target = obj->target;
+    ctx->lam = obj->lambda_grad;
+    ctx->has_obj = true;
+    return TOF_OK;
+}
+
+tof_status tof_field(tof_ctx *ctx, const void *rho, void *H, int32_t comps_mask, void *stream)
+{
+    tof_status s = check_ready(ctx, false);
+    if (s != TOF_OK) return s;
+    if (!rho || !H) return fail(ctx, TOF_ERR_INVALID, "rho and H must be non-null");
+    if (comps_mask < 1 || comps_mask > 7) return fail(ctx, TOF_ERR_INVALID, "comps_mask must be in [1, 7]");
+    hipStream_t st = (hipStream_t)stream;
+    return ctx->f64 ? run_field<double>(ctx, st, rho, H, comps_mask) : run_field<float>(ctx, st, rho, H, comps_mask);
+}
+
+tof_status tof_objective_and_grad(tof_ctx *ctx, const void *rho, double *J, void *grad, void *stream)
+{
+    tof_status s = check_ready(ctx, true);
+    if (s != TOF_OK) return s;
+    if (!rho || !grad) return fail(ctx, TOF_ERR_INVALID, "rho and grad must be non-null");
+    hipStream_t st = (hipStream_t)stream;
+    return ctx->f64 ? run_objective_and_grad<double>(ctx, st, rho, J, grad)
+                    : run_objective_and_grad<float>(ctx, st, rho, J, grad);
+}
+
+tof_status tof_adjoint(tof_ctx *ctx, const void *rho, const void *gH, void *grad, void *stream)
+{
+    tof_status s = check_ready(ctx, false);
+    if (s != TOF_OK) return s;
+    if (!rho || !gH || !grad) return fail(ctx, TOF_ERR_INVALID, "rho, gH and grad must be non-null");
+    hipStream_t st = (hipStream_t)stream;
+    const long long n = (long long)ctx->nx * ctx->ny * ctx->nz;
+    const Box all{0, ctx->nx, 0, ctx->ny, 0, ctx->nz};
+    if (ctx->f64) {
+        View4<const double> src{(const double *)gH, n, (long long)ctx->ny * ctx->nx, ctx->nx, 0, 0, 0};
+        return adjoint_to_grad<double>(ctx, st, rho, src, all, 7, grad);
+    }
+    View4<const float> src{(const float *)gH, n, (long long)ctx->ny * ctx->nx, ctx->nx, 0, 0, 0};
+    return adjoint_to_grad<float>(ctx, st, rho, src, all, 7, grad);
+}
+
+tof_status tof_project_step(tof_ctx *ctx, void *rho, const void *grad, double alpha, void *stream)
+{
+    tof_status s = check_ready(ctx, false);
+    if (s != TOF_OK) return s;
+    if (!rho || !grad) return fail(ctx, TOF_ERR_INVALID, "rho and grad must be non-null");
+    if (!std::isfinite(alpha) || alpha < 0) return fail(ctx, TOF_ERR_INVALID, "alpha must be finite and >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long *mb = (unsigned long long *)ctx->scratch64.p;
+    if (ctx->f64)
+        HIP_TRY(ctx, launch_project_step<double>(st, (double *)rho, (const double *)grad, ctx->nx, ctx->ny, ctx->nz,
+                                                 ctx->design, alpha, mb));
+    else
+        HIP_TRY(ctx, launch_project_step<float>(st, (float *)rho, (const float *)grad, ctx->nx, ctx->ny, ctx->nz,
+                                                ctx->design, alpha, mb));
+    return TOF_OK;
+}
+
+tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (!N) return fail(ctx, TOF_ERR_INVALID, "N is null");
+    hipStream_t st = (hipStream_t)stream;
+    const int lx = ctx->nx + 1, ly = ctx->ny + 1, lz = ctx->nz + 1;
+    DeviceBuf lat;
+    tof_status s = dev_alloc(ctx, lat, sizeof(double) * 2 * (size_t)lx * ly * lz);
+    if (s != TOF_OK) return s;
+    const size_t plane = (size_t)ctx->nx * ctx->ny * ctx->nz;
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
+        e = launch_newell_lattice(st, c, lx, ly, lz, ctx->dx, ctx->dy, ctx->dz, (double *)lat.p);
+        if (e == hipSuccess)
+            e = launch_newell_stencil(st, c, ctx->nx, ctx->ny, ctx->nz, lx, ly, ctx->dx, ctx->dy, ctx->dz,
+                                      (const double *)lat.p, nullptr, ctx->Lx, ctx->Ly, ctx->Lz, N + c * plane);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(lat.p);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tof_tensor");
+    return TOF_OK;
+}
+
+tof_status tof_profile_enable(tof_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (enable && ctx->prof_ev.empty()) {
+        ctx->prof_ev.resize((size_t)TOF_PROFILE_SLOTS * kProfCalls * 2, nullptr);
+        for (hipEvent_t &ev : ctx->prof_ev) HIP_TRY(ctx, hipEventCreate(&ev));
+    }
+    ctx->prof_on = enable != 0;
+    return TOF_OK;
+}
+
+tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[], double bytes_host[])
+{
+    if (!ctx || !ms_host || !count_host || !bytes_host) return fail(ctx, TOF_ERR_INVALID, "null argument");
+    for (int slot = 0; slot < TOF_PROFILE_SLOTS; ++slot) {
+        double sum = 0.0;
+        for (int i = 0; i < ctx->prof_calls[slot]; ++i) {
+            hipEvent_t *ev = &ctx->prof_ev[((size_t)slot * kProfCalls + i) * 2];
+            HIP_TRY(ctx, hipEventSynchronize(ev[1]));
+            float ms = 0.f;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]));
+            sum += ms;
+        }
+        ms_host[slot] = sum;
+        count_host[slot] = ctx->prof_calls[slot];
+        bytes_host[slot] = ctx->prof_bytes[slot];
+        ctx->prof_calls[slot] = 0;
+    }
+    return TOF_OK;
+}
+
+tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3])
+{
+    if (!ctx || !out) return fail(nullptr, TOF_ERR_INVALID, "null argument");
+    out[0] = ctx->Lx;
+    out[1] = ctx->Ly;
+    out[2] = ctx->Lz;
+    return TOF_OK;
+}
+
+size_t tof_workspace_bytes(const tof_ctx *ctx)
+{
+    if (!ctx) return 0;
+    return ctx->spec.bytes + ctx->A.bytes + ctx->B.bytes + ctx->C.bytes + ctx->Hs.bytes + ctx->G.bytes +
+           ctx->Ht.bytes + ctx->scratch64.bytes;
+}
+
+const char *tof_last_error(const tof_ctx *ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_thread_error.c_str();
+}
+
+double tof_dd_newell_host(int32_t c, int32_t kx, int32_t ky, int32_t kz, double dx, double dy, double dz)
+{
+    if (c < 0 || c > 5 || kx < 0 || ky < 0 || kz < 0 || !(dx > 0) || !(dy > 0) || !(dz > 0)) return NAN;
+    const bool ox = comp_odd_x(c), oy = comp_odd_y(c), oz = comp_odd_z(c);
+    dd acc = dd_make(0.0);
+    for (int sz = -1; sz <= 1; ++sz)
+        for (int sy = -1; sy <= 1; ++sy)
+            for (int sx = -1; sx <= 1; ++sx) {
+                int a = kx + sx, b = ky + sy, e = kz + sz;
+                int sign = 1;
+                if (a < 0) { a = -a; if (ox) sign = -sign; }
+                if (b < 0) { b = -b; if (oy) sign = -sign; }
+                if (e < 0) { e = -e; if (oz) sign = -sign; }
+                const int w = (sx ? -1 : 2) * (sy ? -1 : 2) * (sz ? -1 : 2) * sign;
+                const dd v = newell_component_dd(c, two_prod((double)a, dx), two_prod((double)b, dy),
+                                                 two_prod((double)e, dz));
+                acc = dd_add(acc, dd_mul_d(v, (double)w));
+            }
+    return dd_mul(acc, inv_4pi_volume(dx, dy, dz)).hi;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal interface between the C-ABI host code (api.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft.h"
+
+struct Box {
+    int x0, x1, y0, y1, z0, z1;
+    __host__ __device__ int nx() const { return x1 - x0; }
+    __host__ __device__ int ny() const { return y1 - y0; }
+    __host__ __device__ int nz() const { return z1 - z0; }
+    __host__ __device__ bool has(int x, int y, int z) const
+    {
+        return x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1;
+    }
+};
+
+// Where the first (x) pass takes its source values from.
+enum SrcMode {
+    SRC_RHO_SCALAR = 0,   // chi rho^p          (uniform M0 folded into the spectrum coefficients)
+    SRC_RHO_VECTOR = 1,   // chi rho^p M0_c(x)  (spatially varying M0)
+    SRC_ARRAY = 2         // src[c][z][y][x] of a strided array
+};
+
+// Density / magnetization description shared by the first and last passes.
+template <typename R>
+struct DesignDev {
+    const R *rho;          // [nz][ny][nx]
+    const uint8_t *mask;   // optional [nz][ny][nx]
+    const R *m0f;          // optional [3][nz][ny][nx]
+    Box design;
+    int p;
+    int nx, ny, nz;
+};
+
+// Strided 4-D array view: a[c*cs + (z-oz)*zs + (y-oy)*ys + (x-ox)].
+template <typename T>
+struct View4 {
+    T *ptr;
+    long long cs, zs, ys;
+    int ox, oy, oz;
+};
+
+// Spectrum product coefficients: out_o = sum_i C_oi in_i with
+// C = U K V, K the 3x3 symmetric tensor spectrum at the frequency.
+struct ProductDev {
+    int c_in, c_out;
+    double U[3][3];   // [o][a]
+    double V[3][3];   // [b][i]
+    int need;         // bit mask of tensor components (xx, yy, zz, xy, xz, yz) to load
+};
+
+// Octant-compressed real tensor spectra, [6][hx][Lz/2+1][ky_pitch].
+template <typename R>
+struct SpectrumDev {
+    const R *k;
+    long long comp_stride;
+    int hkz, ky_pitch;
+};
+
+// ---- host launchers (kernels.hip); all enqueue on `st` and return hipError_t ----
+
+template <typename R>
+hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
+                            Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx);
+
+template <typename R>
+hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
+                           long long in_outer, long long in_inner, long long out_outer,
+                           long long out_inner, int p_in, int n_in, int p_out, int n_out,
+                           const FftPlanDev &plan, bool inv);
+
+template <typename R>
+hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
+                         int zt0, int nzt, const SpectrumDev<R> &spec, const ProductDev &prod,
+                         bool forward_only, const FftPlanDev &plan);
+
+template <typename R>
+hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
+                            const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
+                            const DesignDev<R> &dsg, const R *m0u, R *grad);
+
+template <typename R>
+hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box keep);
+
+template <typename R>
+hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,
+                            double target, double lam, double dx, double dy, double vcell,
+                            const double *h_target, double *J, R *g);
+
+template <typename R>
+hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, int nx, int ny, int nz,
+                               Box design, double alpha, unsigned long long *maxbits);
+
+hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, double dx,
+                                 double dy, double dz, double *lat /* [lz][ly][lx][2] */);
+
+hipError_t launch_newell_stencil(hipStream_t st, int c, int mx, int my, int mz, int lx, int ly,
+                                 double dx, double dy, double dz, const double *lat,
+                                 double *wrapped, int Lx, int Ly, int Lz, double *octant);
+
+template <typename R>
+hipError_t launch_extract_spectrum(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Lz,
+                                   double scale, R *spec, int hkz, int ky_pitch,
+                                   unsigned long long *imag_max_bits, unsigned long long *real_max_bits);

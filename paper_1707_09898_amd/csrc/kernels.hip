@@ -1,0 +1,776 @@
+// HIP kernels of the gradient engine (gfx950).
+//
+// One convolution H = -N (*) M (eq. (convolution)) runs as five passes over
+// the zero-padded box (L = padded lengths, hx = Lx/2 + 1):
+//   x_forward   source rows -> real-to-complex FFT along x       A[c][kx][z][y]
+//   line_fft    complex FFT along y (source rows only)           B[c][kx][z][ky]
+//   z_pass      FFT along z, spectral tensor product, inverse z  B (in place)
+//   line_fft    inverse FFT along y, target rows only            C[c][kx][z][y]
+//   x_inverse   complex-to-real inverse FFT along x + epilogue   H or dJ/drho
+// The zero padding is never stored: each pass fills it in LDS.  Source and
+// target index boxes restrict every pass to the rows that carry data or are
+// read afterwards (the convolution's result at a target cell does not depend
+// on which other targets are computed).  The tensor spectra are real (each
+// component is even or odd along each axis) and stored for one octant of
+// frequencies with -1/(Lx Ly Lz) folded in, so no pass normalizes.
+#include <hip/hip_runtime.h>
+
+#include "dd.h"
+#include "engine.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename R>
+__device__ __forceinline__ R ipow_dev(R x, int p)
+{
+    R v = (R)1;
+    for (int i = 0; i < p; ++i) v *= x;
+    return v;
+}
+
+template <typename R>
+__device__ __forceinline__ R source_value(int mode, const DesignDev<R> &d, const View4<const R> &s,
+                                          int c, int x, int y, int z)
+{
+    if (mode == SRC_ARRAY)
+        return s.ptr[c * s.cs + (long long)(z - s.oz) * s.zs + (long long)(y - s.oy) * s.ys + (x - s.ox)];
+    if (!d.design.has(x, y, z)) return (R)0;
+    const long long idx = ((long long)z * d.ny + y) * d.nx + x;
+    if (d.mask && !d.mask[idx]) return (R)0;
+    R v = ipow_dev(d.rho[idx], d.p);
+    if (mode == SRC_RHO_VECTOR) v *= d.m0f[(long long)c * d.nx * d.ny * d.nz + idx];
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: real-to-complex FFT along x of TY source rows (one z, one component).
+// Two real rows share one complex line (a + i b); the two half spectra are
+// separated with A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i.
+// Output A[c][kx][z - S.z0][y - S.y0].
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_x_forward(int mode, DesignDev<R> dsg, View4<const R> src,
+                                                      Box S, FftPlanDev plan, cplx<R> *out, int hx,
+                                                      int TY, int pitch)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R> *buf0 = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf1 = buf0 + (TY / 2) * pitch;
+    const int L = plan.L;
+    const int c = blockIdx.z;
+    const int zrel = blockIdx.y;
+    const int z = S.z0 + zrel;
+    const int ybase = S.y0 + blockIdx.x * TY;
+    const int nrow = min(TY, S.y1 - ybase);
+    const int nline = (nrow + 1) / 2;
+    for (int e = threadIdx.x; e < nline * L; e += blockDim.x) {
+        const int l = e / L;
+        const int pos = e - l * L;
+        R re = 0, im = 0;
+        if (pos >= S.x0 && pos < S.x1) {
+            const int r0 = 2 * l;
+            if (r0 < nrow) re = source_value(mode, dsg, src, c, pos, ybase + r0, z);
+            if (r0 + 1 < nrow) im = source_value(mode, dsg, src, c, pos, ybase + r0 + 1, z);
+        }
+        buf0[l * pitch + pos] = cplx<R>{re, im};
+    }
+    __syncthreads();
+    const cplx<R> *res = fft_lines_lds(buf0, buf1, nline, pitch, plan, false);
+    const int nys = S.ny(), nzs = S.nz();
+    const long long kxs = (long long)nzs * nys;
+    cplx<R> *o = out + (long long)c * hx * kxs + (long long)zrel * nys + (ybase - S.y0);
+    const R half = (R)0.5;
+    for (int e = threadIdx.x; e < hx * nrow; e += blockDim.x) {
+        const int k = e / nrow;
+        const int r = e - k * nrow;
+        const cplx<R> *line = res + (r >> 1) * pitch;
+        const cplx<R> Zk = line[k];
+        const cplx<R> Zm = line[k == 0 ? 0 : L - k];
+        cplx<R> v;
+        if ((r & 1) == 0) v = cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half};
+        else v = cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
+        o[k * kxs + r] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Passes 2 and 4: complex FFT of contiguous lines.  Line l reads n_in values
+// at in[(l / inner) in_outer + (l % inner) in_inner] into positions
+// [p_in, p_in + n_in) (zero elsewhere) and writes positions [p_out, p_out + n_out).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_line_fft(const cplx<R> *in, cplx<R> *out, int nlines,
+                                                     int inner, long long in_outer, long long in_inner,
+                                                     long long out_outer, long long out_inner, int p_in,
+                                                     int n_in, int p_out, int n_out, FftPlanDev plan,
+                                                     int inv, int NL, int pitch)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R> *buf0 = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf1 = buf0 + NL * pitch;
+    const int L = plan.L;
+    const int l0 = blockIdx.x * NL;
+    const int nl = min(NL, nlines - l0);
+    for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
+        const int l = e / L;
+        const int pos = e - l * L;
+        const int line = l0 + l;
+        cplx<R> v{0, 0};
+        if (pos >= p_in && pos < p_in + n_in)
+            v = in[(long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner + (pos - p_in)];
+        buf0[l * pitch + pos] = v;
+    }
+    __syncthreads();
+    const cplx<R> *res = fft_lines_lds(buf0, buf1, nl, pitch, plan, inv != 0);
+    for (int e = threadIdx.x; e < nl * n_out; e += blockDim.x) {
+        const int l = e / n_out;
+        const int q = e - l * n_out;
+        const int line = l0 + l;
+        out[(long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner + q] =
+            res[l * pitch + p_out + q];
+    }
+}
+
+// Tensor spectrum at one frequency as a full symmetric 3x3 matrix.  The
+// octant holds |ky|, |kz| (kx is never negative in the half spectrum); odd
+// components change sign with the frequency along their odd axes.
+template <typename R>
+__device__ __forceinline__ void spectrum_at(const SpectrumDev<R> &sp, int need, int kx, int kyq,
+                                            int kzq, R sy, R sz, R K[3][3])
+{
+    R v[6];
+    const long long at = ((long long)kx * sp.hkz + kzq) * sp.ky_pitch + kyq;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = (need >> c & 1) ? sp.k[c * sp.comp_stride + at] : (R)0;
+    v[3] *= sy;        // xy: odd in y
+    v[4] *= sz;        // xz: odd in z
+    v[5] *= sy * sz;   // yz: odd in y and z
+    K[0][0] = v[0]; K[1][1] = v[1]; K[2][2] = v[2];
+    K[0][1] = K[1][0] = v[3];
+    K[0][2] = K[2][0] = v[4];
+    K[1][2] = K[2][1] = v[5];
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: for TK consecutive ky columns of one kx: forward FFT along z of the
+// source rows, per-frequency product out_o = sum_i (U K V)_oi in_i, inverse
+// FFT along z, store the target rows.  In place in B; a block owns its
+// columns, and reads all of them before it writes.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_z_pass(cplx<R> *B, int hx, int Ly, int Zrows, int zs0,
+                                                   int nzs, int zt0, int nzt, SpectrumDev<R> spec,
+                                                   ProductDev prod, int forward_only, FftPlanDev plan,
+                                                   int TK, int pitch)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int cmax = max(prod.c_in, prod.c_out);
+    cplx<R> *buf0 = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf1 = buf0 + cmax * TK * pitch;
+    const int L = plan.L;
+    const int kx = blockIdx.y;
+    const int k0 = blockIdx.x * TK;
+    const int ncol = min(TK, Ly - k0);
+    const long long cstride = (long long)hx * Zrows * Ly;
+    cplx<R> *base = B + (long long)kx * Zrows * Ly + k0;
+    const int c_in = prod.c_in, c_out = prod.c_out;
+    for (int e = threadIdx.x; e < c_in * L * TK; e += blockDim.x) {
+        const int col = e % TK;
+        const int rest = e / TK;
+        const int pos = rest % L;
+        const int i = rest / L;
+        cplx<R> v{0, 0};
+        if (col < ncol && pos >= zs0 && pos < zs0 + nzs) v = base[i * cstride + (long long)(pos - zs0) * Ly + col];
+        buf0[(i * TK + col) * pitch + pos] = v;
+    }
+    __syncthreads();
+    cplx<R> *res = fft_lines_lds(buf0, buf1, c_in * TK, pitch, plan, false);
+    if (forward_only) {
+        for (int e = threadIdx.x; e < c_in * L * TK; e += blockDim.x) {
+            const int col = e % TK;
+            const int rest = e / TK;
+            const int pos = rest % L;
+            const int i = rest / L;
+            if (col < ncol) base[i * cstride + (long long)pos * Ly + col] = res[(i * TK + col) * pitch + pos];
+        }
+        return;
+    }
+    cplx<R> *other = (res == buf0) ? buf1 : buf0;
+    R U[3][3], V[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            U[a][b] = (R)prod.U[a][b];
+            V[a][b] = (R)prod.V[a][b];
+        }
+    const int hLy = Ly / 2, hLz = L / 2;
+    for (int e = threadIdx.x; e < TK * L; e += blockDim.x) {
+        const int col = e % TK;
+        const int kz = e / TK;
+        const int ky = min(k0 + col, Ly - 1);
+        const int kyq = ky <= hLy ? ky : Ly - ky;
+        const int kzq = kz <= hLz ? kz : L - kz;
+        const R sy = ky > hLy ? (R)-1 : (R)1;
+        const R sz = kz > hLz ? (R)-1 : (R)1;
+        R K[3][3];
+        spectrum_at(spec, prod.need, kx, kyq, kzq, sy, sz, K);
+        // KV[a][i] = sum_b K[a][b] V[b][i]
+        R KV[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) KV[a][i] = K[a][0] * V[0][i] + K[a][1] * V[1][i] + K[a][2] * V[2][i];
+        cplx<R> in[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) in[i] = i < c_in ? res[(i * TK + col) * pitch + kz] : cplx<R>{0, 0};
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            if (o >= c_out) break;
+            cplx<R> acc{0, 0};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const R coef = U[o][0] * KV[0][i] + U[o][1] * KV[1][i] + U[o][2] * KV[2][i];
+                acc.x += coef * in[i].x;
+                acc.y += coef * in[i].y;
+            }
+            other[(o * TK + col) * pitch + kz] = acc;
+        }
+    }
+    __syncthreads();
+    const cplx<R> *res2 = fft_lines_lds(other, res, c_out * TK, pitch, plan, true);
+    for (int e = threadIdx.x; e < c_out * nzt * TK; e += blockDim.x) {
+        const int col = e % TK;
+        const int rest = e / TK;
+        const int zq = rest % nzt;
+        const int o = rest / nzt;
+        if (col < ncol) base[o * cstride + (long long)zq * Ly + col] = res2[(o * TK + col) * pitch + zt0 + zq];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 5: complex-to-real inverse FFT along x of TY target rows (one z, all
+// components).  Two Hermitian half spectra A, B become one complex line
+// Z = A + iB (extended by Z[L-k] = conj A[k] + i conj B[k]); the real and
+// imaginary parts of its inverse transform are the two rows.  Epilogue:
+// the field (strided store) or dJ/drho = chi p rho^(p-1) sum_c coef_c A_c over
+// whole x rows (zero outside the design region).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_x_inverse(const cplx<R> *C, int hx, int nc, Box T,
+                                                      FftPlanDev plan, int grad_epi, View4<R> out,
+                                                      DesignDev<R> dsg, R m0u0, R m0u1, R m0u2,
+                                                      R *grad, int TY, int pitch)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int nlmax = TY / 2;
+    cplx<R> *buf0 = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *buf1 = buf0 + nc * nlmax * pitch;
+    const int L = plan.L;
+    const int zrel = blockIdx.y;
+    const int z = T.z0 + zrel;
+    const int ybase = T.y0 + blockIdx.x * TY;
+    const int nrow = min(TY, T.y1 - ybase);
+    const int nline = (nrow + 1) / 2;
+    const int nyt = T.ny(), nzt = T.nz();
+    // stage the half spectra as [c][r][k] in buf1 (pitch >= L + 2 makes it fit)
+    cplx<R> *stage = buf1;
+    for (int e = threadIdx.x; e < nc * hx * nrow; e += blockDim.x) {
+        const int r = e % nrow;
+        const int rest = e / nrow;
+        const int k = rest % hx;
+        const int cc = rest / hx;
+        stage[(cc * TY + r) * hx + k] =
+            C[((long long)(cc * hx + k) * nzt + zrel) * nyt + (ybase - T.y0 + r)];
+    }
+    __syncthreads();
+    const int hL = L / 2;
+    for (int e = threadIdx.x; e < nc * nline * L; e += blockDim.x) {
+        const int pos = e % L;
+        const int rest = e / L;
+        const int l = rest % nline;
+        const int cc = rest / nline;
+        const int rA = 2 * l, rB = 2 * l + 1;
+        cplx<R> a, b;
+        if (pos <= hL) {
+            a = stage[(cc * TY + rA) * hx + pos];
+            b = rB < nrow ? stage[(cc * TY + rB) * hx + pos] : cplx<R>{0, 0};
+            if (pos == 0 || pos == hL) {
+                a.y = 0;
+                b.y = 0;
+            }
+        } else {
+            const int q = L - pos;
+            a = cconj(stage[(cc * TY + rA) * hx + q]);
+            b = rB < nrow ? cconj(stage[(cc * TY + rB) * hx + q]) : cplx<R>{0, 0};
+        }
+        buf0[(cc * nline + l) * pitch + pos] = cplx<R>{a.x - b.y, a.y + b.x};
+    }
+    __syncthreads();
+    const cplx<R> *res = fft_lines_lds(buf0, buf1, nc * nline, pitch, plan, true);
+    if (!grad_epi) {
+        const int nxt = T.nx();
+        for (int e = threadIdx.x; e < nc * nrow * nxt; e += blockDim.x) {
+            const int xq = e % nxt;
+            const int rest = e / nxt;
+            const int r = rest % nrow;
+            const int cc = rest / nrow;
+            const cplx<R> v = res[(cc * nline + (r >> 1)) * pitch + T.x0 + xq];
+            const int y = ybase + r;
+            out.ptr[cc * out.cs + (long long)(z - out.oz) * out.zs + (long long)(y - out.oy) * out.ys +
+                    (T.x0 + xq - out.ox)] = (r & 1) ? v.y : v.x;
+        }
+    } else {
+        const int nx = dsg.nx;
+        const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
+        const R m0u[3] = {m0u0, m0u1, m0u2};
+        for (int e = threadIdx.x; e < nrow * nx; e += blockDim.x) {
+            const int x = e % nx;
+            const int r = e / nx;
+            const int y = ybase + r;
+            const long long idx = ((long long)z * dsg.ny + y) * nx + x;
+            R gval = 0;
+            if (x >= T.x0 && x < T.x1 && dsg.design.has(x, y, z) && (!dsg.mask || dsg.mask[idx])) {
+                R s = 0;
+                for (int cc = 0; cc < nc; ++cc) {
+                    const cplx<R> v = res[(cc * nline + (r >> 1)) * pitch + x];
+                    const R a = (r & 1) ? v.y : v.x;
+                    const R coef = dsg.m0f ? dsg.m0f[cc * ncell + idx] : m0u[cc];
+                    s += coef * a;
+                }
+                gval = (R)dsg.p * ipow_dev(dsg.rho[idx], dsg.p - 1) * s;
+            }
+            grad[idx] = gval;
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_zero_outside(R *a, int nx, int ny, int nz, Box keep)
+{
+    const int row = blockIdx.x;
+    const int y = row % ny;
+    const int z = row / ny;
+    if (y >= keep.y0 && y < keep.y1 && z >= keep.z0 && z < keep.z1) return;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) a[(long long)row * nx + x] = (R)0;
+}
+
+// ---------------------------------------------------------------------------
+// Objective J(H) in FP64 with a fixed-order reduction (deterministic), and
+// g = dJ/dH (exact derivative of the discrete J) on the whole objective box.
+// Hs: [c_j][ob] dense (c_j = 1: Hz only; 3: Hx, Hy, Hz).
+constexpr int kObjThreads = 1024;
+
+template <typename R>
+__device__ __forceinline__ double hval(const R *Hs, const Box &ob, int cc, int x, int y, int z)
+{
+    const long long n = (long long)ob.nx() * ob.ny() * ob.nz();
+    return (double)Hs[cc * n + ((long long)(z - ob.z0) * ob.ny() + (y - ob.y0)) * ob.nx() + (x - ob.x0)];
+}
+
+template <typename R>
+__device__ __forceinline__ double dx_at(const R *Hs, const Box &ob, int x, int y, int z, double dx)
+{
+    return (hval(Hs, ob, 0, x + 1, y, z) - hval(Hs, ob, 0, x - 1, y, z)) / (2.0 * dx);
+}
+
+template <typename R>
+__device__ __forceinline__ double dy_at(const R *Hs, const Box &ob, int x, int y, int z, double dy)
+{
+    return (hval(Hs, ob, 0, x, y + 1, z) - hval(Hs, ob, 0, x, y - 1, z)) / (2.0 * dy);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs, Box ob, Box sb, int c_j,
+                                                         double t, double lam, double dx, double dy,
+                                                         double vcell, const double *ht, double *J, R *g)
+{
+    __shared__ double red[kObjThreads];
+    const int S = sb.nx() * sb.ny() * sb.nz();
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        const int x = sb.x0 + s % sb.nx();
+        const int y = sb.y0 + (s / sb.nx()) % sb.ny();
+        const int z = sb.z0 + s / (sb.nx() * sb.ny());
+        if (kind == 3) {
+            for (int cc = 0; cc < 3; ++cc) {
+                const double d = hval(Hs, ob, cc, x, y, z) - ht[(long long)cc * S + s];
+                acc += d * d;
+            }
+        } else if (kind == 4) {
+            const double h = hval(Hs, ob, 0, x, y, z);
+            acc += h * h;
+        } else {
+            const double d = hval(Hs, ob, 0, x, y, z) - t;
+            acc += d * d;
+            if (kind == 2) {
+                const double gx = dx_at(Hs, ob, x, y, z, dx);
+                const double gy = dy_at(Hs, ob, x, y, z, dy);
+                acc += lam * (gx * gx + gy * gy);
+            }
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && J) *J = (kind == 4) ? -0.5 * vcell * red[0] : red[0] / (double)S;
+
+    const long long nob = (long long)ob.nx() * ob.ny() * ob.nz();
+    const double invS = 1.0 / (double)S;
+    for (long long q = threadIdx.x; q < c_j * nob; q += blockDim.x) {
+        const int cc = (int)(q / nob);
+        const long long w = q % nob;
+        const int x = ob.x0 + (int)(w % ob.nx());
+        const int y = ob.y0 + (int)((w / ob.nx()) % ob.ny());
+        const int z = ob.z0 + (int)(w / ((long long)ob.nx() * ob.ny()));
+        const bool in = sb.has(x, y, z);
+        double v = 0.0;
+        if (kind == 3) {
+            if (in) {
+                const int s = ((z - sb.z0) * sb.ny() + (y - sb.y0)) * sb.nx() + (x - sb.x0);
+                v = 2.0 * (hval(Hs, ob, cc, x, y, z) - ht[(long long)cc * S + s]) * invS;
+            }
+        } else if (kind == 4) {
+            if (in) v = -vcell * hval(Hs, ob, 0, x, y, z);
+        } else {
+            if (in) v = 2.0 * (hval(Hs, ob, 0, x, y, z) - t) * invS;
+            if (kind == 2) {
+                // transpose of the central differences: the sensor cells s = (x -+ 1, y)
+                // and (x, y -+ 1) whose difference reads this cell
+                const double cxs = lam * invS / dx, cys = lam * invS / dy;
+                if (sb.has(x - 1, y, z)) v += cxs * dx_at(Hs, ob, x - 1, y, z, dx);
+                if (sb.has(x + 1, y, z)) v -= cxs * dx_at(Hs, ob, x + 1, y, z, dx);
+                if (sb.has(x, y - 1, z)) v += cys * dy_at(Hs, ob, x, y - 1, z, dy);
+                if (sb.has(x, y + 1, z)) v -= cys * dy_at(Hs, ob, x, y + 1, z, dy);
+            }
+        }
+        g[q] = (R)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Projected gradient step on the design box.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_absmax(const R *grad, int nx, int ny, Box d,
+                                                   unsigned long long *maxbits)
+{
+    const long long n = (long long)d.nx() * d.ny() * d.nz();
+    double m = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = d.x0 + (int)(i % d.nx());
+        const int y = d.y0 + (int)((i / d.nx()) % d.ny());
+        const int z = d.z0 + (int)(i / ((long long)d.nx() * d.ny()));
+        m = fmax(m, fabs((double)grad[((long long)z * ny + y) * nx + x]));
+    }
+    // non-negative doubles order like their bit patterns
+    atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_clear_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_project(R *rho, const R *grad, int nx, int ny, Box d,
+                                                    double alpha, const unsigned long long *maxbits)
+{
+    const double gmax = __longlong_as_double((long long)*maxbits);
+    if (!(gmax > 0.0)) return;
+    const double step = alpha / gmax;
+    const long long n = (long long)d.nx() * d.ny() * d.nz();
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = d.x0 + (int)(i % d.nx());
+        const int y = d.y0 + (int)((i / d.nx()) % d.ny());
+        const int z = d.z0 + (int)(i / ((long long)d.nx() * d.ny()));
+        const long long idx = ((long long)z * ny + y) * nx + x;
+        const R v = rho[idx] - (R)(step * (double)grad[idx]);
+        rho[idx] = v < (R)0 ? (R)0 : (v > (R)1 ? (R)1 : v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tensor setup (FP64, double-double).
+__global__ __launch_bounds__(128) void k_newell_lattice(int c, int lx, int ly, int lz, double dx,
+                                                      double dy, double dz, double *lat)
+{
+    const long long n = (long long)lx * ly * lz;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % lx);
+        const int j = (int)((q / lx) % ly);
+        const int k = (int)(q / ((long long)lx * ly));
+        // lattice coordinates i*dx exactly (a double-double product is exact)
+        const dd X = two_prod((double)i, dx), Y = two_prod((double)j, dy), Z = two_prod((double)k, dz);
+        const dd v = newell_component_dd(c, X, Y, Z);
+        lat[2 * q] = v.hi;
+        lat[2 * q + 1] = v.lo;
+    }
+}
+
+// N_c(k) for 0 <= k < m: separable (-1, 2, -1) second difference of the
+// lattice values, times 1/(4 pi V), summed in double-double and rounded once.
+// Writes the octant (if `octant`) and/or the wrapped periodic array (if
+// `wrapped`): offset -k sits at L - k, with the component's parity sign.
+__global__ __launch_bounds__(128) void k_newell_stencil(int c, int mx, int my, int mz, int lx, int ly,
+                                                      dd scale, const double *lat, double *wrapped,
+                                                      int Lx, int Ly, int Lz, double *octant)
+{
+    const long long n = (long long)mx * my * mz;
+    const bool ox = comp_odd_x(c), oy = comp_odd_y(c), oz = comp_odd_z(c);
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % mx);
+        const int j = (int)((q / mx) % my);
+        const int k = (int)(q / ((long long)mx * my));
+        dd acc = dd_make(0.0);
+        for (int sz = -1; sz <= 1; ++sz)
+            for (int sy = -1; sy <= 1; ++sy)
+                for (int sx = -1; sx <= 1; ++sx) {
+                    int a = i + sx, b = j + sy, e = k + sz;
+                    int sign = 1;
+                    if (a < 0) { a = -a; if (ox) sign = -sign; }
+                    if (b < 0) { b = -b; if (oy) sign = -sign; }
+                    if (e < 0) { e = -e; if (oz) sign = -sign; }
+                    const int w = (sx ? -1 : 2) * (sy ? -1 : 2) * (sz ? -1 : 2) * sign;
+                    const long long at = ((long long)e * ly + b) * lx + a;
+                    const dd v{lat[2 * at], lat[2 * at + 1]};
+                    acc = dd_add(acc, dd_mul_d(v, (double)w));
+                }
+        const double val = dd_mul(acc, scale).hi;
+        if (octant) octant[q] = val;
+        if (wrapped) {
+            for (int fz = 0; fz < 2; ++fz) {
+                if (fz && k == 0) continue;
+                for (int fy = 0; fy < 2; ++fy) {
+                    if (fy && j == 0) continue;
+                    for (int fx = 0; fx < 2; ++fx) {
+                        if (fx && i == 0) continue;
+                        const int px = fx ? Lx - i : i, py = fy ? Ly - j : j, pz = fz ? Lz - k : k;
+                        double s = 1.0;
+                        if (fx && ox) s = -s;
+                        if (fy && oy) s = -s;
+                        if (fz && oz) s = -s;
+                        wrapped[((long long)pz * Ly + py) * Lx + px] = s * val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Real part of the forward transform on the frequency octant, times `scale`,
+// rounded to the working precision; also the largest |imag| and |real| (bits).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_extract_spectrum(const cplx<double> *B, int hx, int Ly,
+                                                             int Lz, double scale, R *spec, int hkz,
+                                                             int ky_pitch, unsigned long long *mx_imag,
+                                                             unsigned long long *mx_real)
+{
+    const int hky = Ly / 2 + 1;
+    const long long n = (long long)hx * hkz * hky;
+    double mi = 0.0, mr = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int ky = (int)(q % hky);
+        const int kz = (int)((q / hky) % hkz);
+        const int kx = (int)(q / ((long long)hky * hkz));
+        const cplx<double> v = B[((long long)kx * Lz + kz) * Ly + ky];
+        spec[((long long)kx * hkz + kz) * ky_pitch + ky] = (R)(scale * v.x);
+        mi = fmax(mi, fabs(v.y));
+        mr = fmax(mr, fabs(v.x));
+    }
+    atomicMax(mx_imag, (unsigned long long)__double_as_longlong(mi));
+    atomicMax(mx_real, (unsigned long long)__double_as_longlong(mr));
+}
+
+// ---- launch configuration helpers ----
+
+constexpr size_t kLdsBudget = 64 * 1024;
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+template <typename R>
+hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
+                            Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx)
+{
+    const int L = plan.L;
+    const int pitch = L + 1;
+    const size_t per_line = 2 * (size_t)pitch * sizeof(cplx<R>);
+    int TY = 2 * (int)(kLdsBudget / per_line);
+    TY = TY > 32 ? 32 : (TY < 2 ? 2 : TY);
+    const size_t lds = (size_t)(TY / 2) * per_line;
+    hipError_t e = allow_lds(k_x_forward<R>, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((S.ny() + TY - 1) / TY, S.nz(), c_in);
+    hipLaunchKernelGGL(k_x_forward<R>, grid, dim3(kThreads), lds, st, mode, dsg, src, S, plan, out, hx,
+                       TY, pitch);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
+                           long long in_outer, long long in_inner, long long out_outer,
+                           long long out_inner, int p_in, int n_in, int p_out, int n_out,
+                           const FftPlanDev &plan, bool inv)
+{
+    if (nlines <= 0) return hipSuccess;
+    const int pitch = plan.L + 1;
+    const size_t per_line = 2 * (size_t)pitch * sizeof(cplx<R>);
+    int NL = (int)(kLdsBudget / per_line);
+    NL = NL > 16 ? 16 : (NL < 1 ? 1 : NL);
+    const size_t lds = (size_t)NL * per_line;
+    hipError_t e = allow_lds(k_line_fft<R>, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((nlines + NL - 1) / NL);
+    hipLaunchKernelGGL(k_line_fft<R>, grid, dim3(kThreads), lds, st, in, out, nlines, inner, in_outer,
+                       in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, plan, inv ? 1 : 0, NL,
+                       pitch);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
+                         int zt0, int nzt, const SpectrumDev<R> &spec, const ProductDev &prod,
+                         bool forward_only, const FftPlanDev &plan)
+{
+    const int pitch = plan.L + 1;
+    const int cmax = prod.c_in > prod.c_out ? prod.c_in : prod.c_out;
+    const size_t per_col = 2 * (size_t)cmax * pitch * sizeof(cplx<R>);
+    int TK = (int)(kLdsBudget / per_col);
+    TK = TK > 16 ? 16 : (TK < 1 ? 1 : TK);
+    const size_t lds = (size_t)TK * per_col;
+    hipError_t e = allow_lds(k_z_pass<R>, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((Ly + TK - 1) / TK, hx);
+    hipLaunchKernelGGL(k_z_pass<R>, grid, dim3(kThreads), lds, st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt,
+                       spec, prod, forward_only ? 1 : 0, plan, TK, pitch);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
+                            const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
+                            const DesignDev<R> &dsg, const R *m0u, R *grad)
+{
+    const int pitch = plan.L + 2;
+    const size_t per_line = 2 * (size_t)c * pitch * sizeof(cplx<R>);
+    int TY = 2 * (int)(kLdsBudget / per_line);
+    TY = TY > 32 ? 32 : (TY < 2 ? 2 : TY);
+    const size_t lds = (size_t)(TY / 2) * per_line;
+    hipError_t e = allow_lds(k_x_inverse<R>, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((T.ny() + TY - 1) / TY, T.nz());
+    hipLaunchKernelGGL(k_x_inverse<R>, grid, dim3(kThreads), lds, st, C, hx, c, T, plan,
+                       grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, TY, pitch);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box keep)
+{
+    hipLaunchKernelGGL(k_zero_outside<R>, dim3(ny * nz), dim3(kThreads), 0, st, a, nx, ny, nz, keep);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,
+                            double target, double lam, double dx, double dy, double vcell,
+                            const double *h_target, double *J, R *g)
+{
+    hipLaunchKernelGGL(k_objective<R>, dim3(1), dim3(kObjThreads), 0, st, kind, Hs, ob, sensor, c_j,
+                       target, lam, dx, dy, vcell, h_target, J, g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, int nx, int ny, int nz,
+                               Box design, double alpha, unsigned long long *maxbits)
+{
+    (void)nz;
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, maxbits, 1);
+    const long long n = (long long)design.nx() * design.ny() * design.nz();
+    int blocks = (int)((n + kThreads - 1) / kThreads);
+    blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
+    hipLaunchKernelGGL(k_absmax<R>, dim3(blocks), dim3(kThreads), 0, st, grad, nx, ny, design, maxbits);
+    hipLaunchKernelGGL(k_project<R>, dim3(blocks), dim3(kThreads), 0, st, rho, grad, nx, ny, design, alpha,
+                       maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, double dx, double dy,
+                                 double dz, double *lat)
+{
+    const long long n = (long long)lx * ly * lz;
+    int blocks = (int)((n + 127) / 128);
+    blocks = blocks > 65536 ? 65536 : blocks;
+    hipLaunchKernelGGL(k_newell_lattice, dim3(blocks), dim3(128), 0, st, c, lx, ly, lz, dx, dy, dz, lat);
+    return hipGetLastError();
+}
+
+hipError_t launch_newell_stencil(hipStream_t st, int c, int mx, int my, int mz, int lx, int ly, double dx,
+                                 double dy, double dz, const double *lat, double *wrapped, int Lx, int Ly,
+                                 int Lz, double *octant)
+{
+    const long long n = (long long)mx * my * mz;
+    int blocks = (int)((n + 127) / 128);
+    blocks = blocks > 65536 ? 65536 : blocks;
+    const dd scale = inv_4pi_volume(dx, dy, dz);
+    hipLaunchKernelGGL(k_newell_stencil, dim3(blocks), dim3(128), 0, st, c, mx, my, mz, lx, ly, scale, lat,
+                       wrapped, Lx, Ly, Lz, octant);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_extract_spectrum(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Lz,
+                                   double scale, R *spec, int hkz, int ky_pitch, unsigned long long *mi,
+                                   unsigned long long *mr)
+{
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mi, 1);
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mr, 1);
+    const long long n = (long long)hx * hkz * (Ly / 2 + 1);
+    int blocks = (int)((n + kThreads - 1) / kThreads);
+    blocks = blocks > 8192 ? 8192 : blocks;
+    hipLaunchKernelGGL(k_extract_spectrum<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Lz, scale,
+                       spec, hkz, ky_pitch, mi, mr);
+    return hipGetLastError();
+}
+
+#define TOF_INSTANTIATE(R)                                                                              \
+    template hipError_t launch_x_forward<R>(hipStream_t, int, const DesignDev<R> &, View4<const R>, Box, \
+                                            int, const FftPlanDev &, cplx<R> *, int);                    \
+    template hipError_t launch_line_fft<R>(hipStream_t, const cplx<R> *, cplx<R> *, int, int, long long, \
+                                           long long, long long, long long, int, int, int, int,          \
+                                           const FftPlanDev &, bool);                                    \
+    template hipError_t launch_z_pass<R>(hipStream_t, cplx<R> *, int, int, int, int, int, int, int,     \
+                                         const SpectrumDev<R> &, const ProductDev &, bool,               \
+                                         const FftPlanDev &);                                            \
+    template hipError_t launch_x_inverse<R>(hipStream_t, const cplx<R> *, int, int, Box,                 \
+                                            const FftPlanDev &, bool, View4<R>, const DesignDev<R> &,    \
+                                            const R *, R *);                                             \
+    template hipError_t launch_zero_outside<R>(hipStream_t, R *, int, int, int, Box);                    \
+    template hipError_t launch_objective<R>(hipStream_t, int, const R *, Box, Box, int, double, double,  \
+                                            double, double, double, const double *, double *, R *);      \
+    template hipError_t launch_project_step<R>(hipStream_t, R *, const R *, int, int, int, Box, double,  \
+                                               unsigned long long *);                                          \
+    template hipError_t launch_extract_spectrum<R>(hipStream_t, const cplx<double> *, int, int, int,     \
+                                                   double, R *, int, int, unsigned long long *,          \
+                                                   unsigned long long *);
+
+TOF_INSTANTIATE(float)
+TOF_INSTANTIATE(double)

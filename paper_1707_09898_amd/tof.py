@@ -1,0 +1,247 @@
+"""Python binding of the C ABI in include/tof.h (argument marshalling only).
+
+Every step of the gradient evaluation runs in the HIP kernels of libtof.so;
+PyTorch only provides device memory and the current stream.  Importing this
+module does not need a GPU; creating an Engine does, and fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtof.so")
+
+TOF_F32, TOF_F64 = 1, 2
+J_MEAN_SQ_HZ, J_MEAN_SQ_HZ_GRADXY, J_MEAN_SQ_H_TARGET, J_NEG_HALF_HZ2 = 1, 2, 3, 4
+
+STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TOF_ERR_OOM",
+          -4: "TOF_ERR_HIP", -5: "TOF_ERR_NUMERIC", -6: "TOF_ERR_STATE"}
+
+EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "tof_field",
+           "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
+           "tof_padded_lengths", "tof_workspace_bytes", "tof_last_error", "tof_dd_newell_host",
+           "tof_profile_enable", "tof_profile_read"]
+
+PROFILE_SLOTS = 12
+PROFILE_NAMES = ["fwd_x", "fwd_y", "fwd_z_product", "fwd_inv_y", "fwd_inv_x_field", "objective",
+                 "adj_x", "adj_y", "adj_z_product", "adj_inv_y", "adj_inv_x_grad", "zero_fill"]
+# kernel symbol of each slot (as rocprofv3 names it, without template arguments)
+PROFILE_KERNELS = ["k_x_forward", "k_line_fft", "k_z_pass", "k_line_fft", "k_x_inverse", "k_objective",
+                   "k_x_forward", "k_line_fft", "k_z_pass", "k_line_fft", "k_x_inverse", "k_zero_outside"]
+
+
+class TofError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32)]
+
+
+class BoxC(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("x0", "x1", "y0", "y1", "z0", "z1")]
+
+
+class Objective(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("sensor", BoxC), ("target", ctypes.c_double),
+                ("lambda_grad", ctypes.c_double), ("h_target_host", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtof.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.tof_create.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(vp)]
+        L.tof_destroy.argtypes = [vp]
+        L.tof_destroy.restype = None
+        L.tof_set_design.argtypes = [vp, ctypes.POINTER(BoxC), vp, ctypes.POINTER(dbl), vp, i32]
+        L.tof_set_objective.argtypes = [vp, ctypes.POINTER(Objective)]
+        L.tof_field.argtypes = [vp, vp, vp, i32, vp]
+        L.tof_objective_and_grad.argtypes = [vp, vp, vp, vp, vp]
+        L.tof_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.tof_project_step.argtypes = [vp, vp, vp, dbl, vp]
+        L.tof_tensor.argtypes = [vp, vp, vp]
+        L.tof_padded_lengths.argtypes = [vp, ctypes.POINTER(i32)]
+        L.tof_workspace_bytes.argtypes = [vp]
+        L.tof_workspace_bytes.restype = ctypes.c_size_t
+        L.tof_last_error.argtypes = [vp]
+        L.tof_last_error.restype = ctypes.c_char_p
+        L.tof_dd_newell_host.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl]
+        L.tof_dd_newell_host.restype = dbl
+        L.tof_profile_enable.argtypes = [vp, i32]
+        L.tof_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
+        for name in ("tof_create", "tof_set_design", "tof_set_objective", "tof_field",
+                     "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
+                     "tof_padded_lengths", "tof_profile_enable", "tof_profile_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _box(b) -> BoxC:
+    return BoxC(*(int(v) for v in b))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Engine:
+    """One context: a grid, its FFT plans, workspaces and tensor spectra."""
+
+    def __init__(self, n: Sequence[int], h: Sequence[float], dtype: str = "f32",
+                 L: Optional[Sequence[int]] = None, stream=None):
+        import torch
+        self.torch = torch
+        self.n = tuple(int(v) for v in n)
+        self.h = tuple(float(v) for v in h)
+        self.dtype = {"f32": torch.float32, "f64": torch.float64}[dtype]
+        Lx, Ly, Lz = (0, 0, 0) if L is None else (int(v) for v in L)
+        g = Grid(self.n[0], self.n[1], self.n[2], self.h[0], self.h[1], self.h[2], Lx, Ly, Lz,
+                 TOF_F32 if dtype == "f32" else TOF_F64)
+        self._ctx = ctypes.c_void_p()
+        self._keep = {}
+        st = lib().tof_create(ctypes.byref(g), _stream_ptr(stream), ctypes.byref(self._ctx))
+        if st != 0:
+            raise TofError(st, lib().tof_last_error(None).decode())
+
+    # -- helpers --
+    def _check(self, st: int):
+        if st != 0:
+            raise TofError(st, lib().tof_last_error(self._ctx).decode())
+
+    def _arr(self, t, shape, dtype=None):
+        dtype = self.dtype if dtype is None else dtype
+        if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected a contiguous {dtype} cuda tensor of shape {tuple(shape)}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        nx, ny, nz = self.n
+        return (nz, ny, nx)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().tof_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup --
+    def set_design(self, design=None, m0=(0.0, 0.0, 1.0), m0_field=None, p: int = 3, mask=None):
+        bx = ctypes.byref(_box(design)) if design is not None else None
+        m0a = (ctypes.c_double * 3)(*[float(v) for v in m0])
+        mf = self._arr(m0_field, (3,) + self.shape) if m0_field is not None else None
+        mk = self._arr(mask, self.shape, self.torch.uint8) if mask is not None else None
+        self._keep["m0_field"] = m0_field
+        self._keep["mask"] = mask
+        self._check(lib().tof_set_design(self._ctx, bx, mk, m0a, mf, int(p)))
+
+    def set_objective(self, kind: int, sensor, target: float = 0.0, lam: float = 0.0, h_target=None):
+        import numpy as np
+        ptr = None
+        if h_target is not None:
+            ht = np.ascontiguousarray(h_target, dtype=np.float64)
+            self._keep["h_target"] = ht
+            ptr = ht.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        obj = Objective(int(kind), _box(sensor), float(target), float(lam), ptr)
+        self._check(lib().tof_set_objective(self._ctx, ctypes.byref(obj)))
+
+    # -- hot calls --
+    def field(self, rho, comps: int = 7, out=None, stream=None):
+        c = bin(comps).count("1")
+        if out is None:
+            out = self.torch.empty((c,) + self.shape, dtype=self.dtype, device=rho.device)
+        self._check(lib().tof_field(self._ctx, self._arr(rho, self.shape), self._arr(out, (c,) + self.shape),
+                                    int(comps), _stream_ptr(stream)))
+        return out
+
+    def objective_and_grad(self, rho, grad=None, J=None, stream=None):
+        if grad is None:
+            grad = self.torch.empty(self.shape, dtype=self.dtype, device=rho.device)
+        if J is None:
+            J = self.torch.empty((1,), dtype=self.torch.float64, device=rho.device)
+        self._check(lib().tof_objective_and_grad(self._ctx, self._arr(rho, self.shape),
+                                                 self._arr(J, (1,), self.torch.float64),
+                                                 self._arr(grad, self.shape), _stream_ptr(stream)))
+        return J, grad
+
+    def adjoint(self, rho, gH, grad=None, stream=None):
+        if grad is None:
+            grad = self.torch.empty(self.shape, dtype=self.dtype, device=rho.device)
+        self._check(lib().tof_adjoint(self._ctx, self._arr(rho, self.shape), self._arr(gH, (3,) + self.shape),
+                                      self._arr(grad, self.shape), _stream_ptr(stream)))
+        return grad
+
+    def project_step(self, rho, grad, alpha: float, stream=None):
+        self._check(lib().tof_project_step(self._ctx, self._arr(rho, self.shape), self._arr(grad, self.shape),
+                                           float(alpha), _stream_ptr(stream)))
+        return rho
+
+    # -- checks / introspection --
+    def tensor(self, stream=None):
+        N = self.torch.empty((6,) + self.shape, dtype=self.torch.float64, device="cuda")
+        self._check(lib().tof_tensor(self._ctx, ctypes.c_void_p(N.data_ptr()), _stream_ptr(stream)))
+        return N
+
+    def profile(self, enable: bool = True):
+        self._check(lib().tof_profile_enable(self._ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """Per slot: (name, total ms, launches, algorithmic bytes per launch)."""
+        ms = (ctypes.c_double * PROFILE_SLOTS)()
+        cnt = (ctypes.c_int64 * PROFILE_SLOTS)()
+        by = (ctypes.c_double * PROFILE_SLOTS)()
+        self._check(lib().tof_profile_read(self._ctx, ms, cnt, by))
+        return [(PROFILE_NAMES[i], ms[i], cnt[i], by[i]) for i in range(PROFILE_SLOTS)]
+
+    def padded_lengths(self) -> Tuple[int, int, int]:
+        out = (ctypes.c_int32 * 3)()
+        self._check(lib().tof_padded_lengths(self._ctx, out))
+        return tuple(out)
+
+    def workspace_bytes(self) -> int:
+        return int(lib().tof_workspace_bytes(self._ctx))
+
+
+def engine_for(w, dtype: str = "f32", stream=None) -> Engine:
+    """An Engine set up for a workload description (workloads.Workload)."""
+    import torch
+    e = Engine(w.n, w.h, dtype, L=w.pad, stream=stream)
+    tdt = e.dtype
+    m0f = None
+    if w.m0_field is not None:
+        m0f = torch.as_tensor(w.m0_field, dtype=tdt).contiguous().cuda()
+    e.set_design(w.design, m0=w.m0, m0_field=m0f, p=w.p)
+    e.set_objective(w.j_kind, w.sensor, w.j_target, w.j_lambda, w.h_target)
+    return e
+
+
+def newell_host(c: int, k: Sequence[int], h: Sequence[float]) -> float:
+    """The double-double tensor entry the GPU setup computes, evaluated on the host."""
+    return float(lib().tof_dd_newell_host(int(c), int(k[0]), int(k[1]), int(k[2]),
+                                          float(h[0]), float(h[1]), float(h[2])))

@@ -1,0 +1,94 @@
+"""CPU checks of the C-ABI library: it loads without a GPU, exports every
+entry point include/tof.h declares, rejects bad arguments before any HIP call,
+and its host-compiled double-double Newell evaluation (the code the GPU setup
+runs) matches the quad-precision oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_09898_amd import tof
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "tof.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tof_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tof.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(tof.EXPORTS) == names
+
+
+def test_invalid_grids_are_rejected_before_any_launch():
+    L = tof.lib()
+    ctx = ctypes.c_void_p()
+    assert L.tof_create(None, None, ctypes.byref(ctx)) == -1
+    bad = [tof.Grid(0, 4, 4, 1, 1, 1, 0, 0, 0, 1),
+           tof.Grid(4, 4, 4, -1, 1, 1, 0, 0, 0, 1),
+           tof.Grid(4, 4, 4, 1, float("nan"), 1, 0, 0, 0, 1),
+           tof.Grid(4, 4, 4, 1, 1, 1, 0, 0, 0, 3),
+           tof.Grid(600, 4, 4, 1, 1, 1, 0, 0, 0, 1)]
+    for g in bad:
+        assert L.tof_create(ctypes.byref(g), None, ctypes.byref(ctx)) == -1
+        assert ctx.value is None
+        assert len(L.tof_last_error(None)) > 0
+    # padded lengths: too short, odd, or with a prime factor above 7
+    for lengths in [(6, 8, 8), (9, 8, 8), (22, 8, 8)]:
+        g = tof.Grid(4, 4, 4, 1, 1, 1, *lengths, 1)
+        if lengths[0] == 22:
+            g = tof.Grid(11, 4, 4, 1, 1, 1, *lengths, 1)
+        assert L.tof_create(ctypes.byref(g), None, ctypes.byref(ctx)) == -2
+
+
+def test_null_context_calls_fail_cleanly():
+    L = tof.lib()
+    m0 = (ctypes.c_double * 3)(0, 0, 1)
+    assert L.tof_set_design(None, None, None, m0, None, 3) == -1
+    assert L.tof_set_objective(None, None) == -1
+    assert L.tof_field(None, None, None, 7, None) == -1
+    assert L.tof_objective_and_grad(None, None, None, None, None) == -1
+    assert L.tof_adjoint(None, None, None, None, None) == -1
+    assert L.tof_project_step(None, None, None, 0.1, None) == -1
+    assert L.tof_tensor(None, None, None) == -1
+    assert L.tof_workspace_bytes(None) == 0
+    L.tof_destroy(None)
+
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (1.0, 1.0, 0.5), (0.7, 1.3, 2.0), (1.9, 0.55, 1.2)])
+def test_double_double_newell_matches_quad_oracle(h):
+    t = oracle.newell_table((48, 40, 30), h)
+    rng = np.random.default_rng(7)
+    ks = [(0, 0, 0), (1, 0, 0), (0, 1, 1), (47, 39, 29), (3, 2, 1)]
+    ks += [tuple(int(rng.integers(0, m)) for m in (48, 40, 30)) for _ in range(20)]
+    for c in range(6):
+        scale = np.abs(t[c]).max()
+        for k in ks:
+            v = tof.newell_host(c, k, h)
+            assert abs(v - t[c, k[2], k[1], k[0]]) <= 1e-15 * scale, (c, k)
+
+
+def test_double_double_newell_far_offsets():
+    """Offsets where double precision would lose 1e-5 .. 1e-1 relative."""
+    h = (1.0, 1.0, 1.0)
+    t = oracle.newell_table((200, 101, 120), h, comps=[2, 3])
+    for k in [(199, 100, 119), (150, 90, 60), (120, 3, 100)]:
+        for c in (2, 3):
+            want = t[c, k[2], k[1], k[0]]
+            assert abs(tof.newell_host(c, k, h) - want) <= 1e-13 * abs(want) + 1e-300
+
+
+def test_bad_newell_arguments_give_nan():
+    assert np.isnan(tof.newell_host(6, (0, 0, 0), (1, 1, 1)))
+    assert np.isnan(tof.newell_host(0, (-1, 0, 0), (1, 1, 1)))
+    assert np.isnan(tof.newell_host(0, (0, 0, 0), (0, 1, 1)))

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element on seeded inputs (small and ragged sizes that span several tiles),
+and on sampled outputs at the full 256 x 256 x 128 size in the launch
+configuration the benchmark times.
+
+Tolerances (normwise, max|x - ref| / max|ref|): 1e-10 in FP64 and 1e-5 in
+FP32, the accuracy targets of the gradient engine; J relative to |J|.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_09898_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def tof():
+    from paper_1707_09898_amd import tof as m
+    return m
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_inf(x, ref):
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def dev(torch, a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# ---------------------------------------------------------------- tensor setup
+@pytest.mark.parametrize("n,h", [((12, 10, 14), (1.0, 1.0, 1.0)), ((9, 11, 8), (0.7, 1.3, 0.9)),
+                                 ((64, 64, 64), (1.0, 1.0, 0.5))])
+def test_gpu_tensor_matches_oracle(torch, n, h):
+    say("tensor", n, h)
+    e = tof().Engine(n, h, "f64")
+    N = host(e.tensor())
+    ref = oracle.newell_table(n, h)
+    for c in range(6):
+        scale = np.abs(ref[c]).max()
+        assert np.abs(N[c] - ref[c]).max() <= 1e-15 * scale, c
+
+
+# ---------------------------------------------------------------- field
+FIELD_CASES = [
+    ("c1", lambda: wl.config1()),
+    ("ragged", lambda: wl.small_random(21, n=(13, 10, 7), h=(1.0, 0.8, 1.3))),
+    ("vector_m0", lambda: wl.small_random(22, n=(9, 12, 10), varying_m0=True)),
+    ("tilted_m0", lambda: wl.small_random(23, n=(10, 9, 11), m0=(0.3, -0.4, 0.866))),
+    ("nonsmooth", lambda: wl.small_random(24, n=(11, 13, 6), h=(1.0, 1.0, 1.0))),  # 2n = 22, 26: L = 24, 28
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,make", FIELD_CASES)
+def test_gpu_field_matches_direct_sum(torch, name, make, dtype):
+    w = make()
+    say("field", name, dtype, w.n)
+    t = tof()
+    e = t.engine_for(w, dtype)
+    tdt = e.dtype
+    H = host(e.field(dev(torch, w.rho, tdt), comps=7))
+    torch.cuda.synchronize()
+    nx, ny, nz = w.n
+    ref = oracle.field(w.n, w.h, oracle.magnetization(w), w.design, (0, nx, 0, ny, 0, nz),
+                       oracle.m0_mask(w), 7)
+    assert rel_inf(H, ref) <= TOL[dtype], rel_inf(H, ref)
+    # single components in component order
+    Hz = host(e.field(dev(torch, w.rho, tdt), comps=4))
+    assert rel_inf(Hz[0], ref[2]) <= TOL[dtype]
+    Hxz = host(e.field(dev(torch, w.rho, tdt), comps=5))
+    assert rel_inf(Hxz, ref[[0, 2]]) <= TOL[dtype]
+
+
+# ---------------------------------------------------------------- gradient
+GRAD_CASES = [
+    ("c1", lambda: wl.config1()),
+    ("c2", lambda: wl.config2()),
+    ("gradxy_ragged", lambda: wl.small_random(31, n=(17, 13, 11), h=(0.7, 1.3, 0.9))),
+    ("p4", lambda: wl.small_random(32, n=(12, 14, 9), p=4)),
+    ("htarget_vector", lambda: wl.small_random(33, n=(10, 11, 12), j_kind=wl.J_MEAN_SQ_H_TARGET,
+                                               varying_m0=True)),
+    ("neg_half_tilted", lambda: wl.small_random(34, n=(9, 10, 8), j_kind=wl.J_NEG_HALF_HZ2,
+                                                m0=(0.3, -0.4, 0.866))),
+    ("mean_sq_hz_corner", lambda: wl.small_random(35, n=(8, 8, 9), j_kind=wl.J_MEAN_SQ_HZ,
+                                                  sensor=(0, 3, 5, 8, 8, 9))),
+    ("p1_single_design_cell", lambda: wl.small_random(36, n=(7, 6, 8), p=1, design=(3, 4, 2, 3, 1, 2))),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,make", GRAD_CASES)
+def test_gpu_objective_and_grad_match_oracle(torch, name, make, dtype):
+    w = make()
+    say("grad", name, dtype, w.n)
+    e = tof().engine_for(w, dtype)
+    J, g = e.objective_and_grad(dev(torch, w.rho, e.dtype))
+    torch.cuda.synchronize()
+    J = float(J.item())
+    g = host(g)
+    Jr, gr, _ = oracle.objective_and_grad(w)
+    assert abs(J - Jr) <= TOL[dtype] * abs(Jr), (J, Jr)
+    assert rel_inf(g, gr) <= TOL[dtype], rel_inf(g, gr)
+    # zero outside the design region
+    chi = oracle.box_mask(w.n, w.design)
+    assert np.all(g[chi == 0] == 0.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gpu_adjoint_vjp_matches_oracle(torch, dtype):
+    w = wl.small_random(41, n=(11, 9, 10), varying_m0=True)
+    say("adjoint", dtype)
+    e = tof().engine_for(w, dtype)
+    rng = np.random.default_rng(5)
+    gH = rng.normal(size=(3,) + w.rho.shape)
+    grad = host(e.adjoint(dev(torch, w.rho, e.dtype), dev(torch, gH, e.dtype)))
+    nx, ny, nz = w.n
+    A = oracle.field(w.n, w.h, gH, (0, nx, 0, ny, 0, nz), w.design, 7, 7)
+    ref = oracle.gradient_from_adjoint(w, A)
+    assert rel_inf(grad, ref) <= TOL[dtype]
+
+
+def test_gpu_is_deterministic_and_stream_safe(torch):
+    w = wl.config2()
+    e = tof().engine_for(w, "f32")
+    rho = dev(torch, w.rho, torch.float32)
+    J1, g1 = e.objective_and_grad(rho)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        J2, g2 = e.objective_and_grad(rho)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(J1, J2)
+
+
+def test_gpu_project_step(torch):
+    w = wl.small_random(42, n=(10, 9, 8))
+    e = tof().engine_for(w, "f64")
+    rho = dev(torch, w.rho, torch.float64)
+    J, g = e.objective_and_grad(rho)
+    gh = host(g)
+    e.project_step(rho, g, 0.05)
+    torch.cuda.synchronize()
+    x0, x1, y0, y1, z0, z1 = w.design
+    want = w.rho.copy()
+    gm = np.abs(gh[z0:z1, y0:y1, x0:x1]).max()
+    want[z0:z1, y0:y1, x0:x1] = np.clip(w.rho[z0:z1, y0:y1, x0:x1] - 0.05 * gh[z0:z1, y0:y1, x0:x1] / gm, 0, 1)
+    np.testing.assert_allclose(host(rho), want, rtol=0, atol=1e-15)
+
+
+def test_gpu_zero_density(torch):
+    w = wl.config1()
+    w = dataclasses.replace(w, rho=np.zeros_like(w.rho))
+    e = tof().engine_for(w, "f32")
+    J, g = e.objective_and_grad(dev(torch, w.rho, torch.float32))
+    torch.cuda.synchronize()
+    assert abs(J.item() - 0.01) < 1e-15
+    assert torch.count_nonzero(g).item() == 0
+
+
+# ---------------------------------------------------------------- full size, sampled
+def sampled_reference(w, cells):
+    """Oracle J, g on the objective box, and the gradient at sampled cells."""
+    table = oracle.table_for(w)
+    H = oracle.forward_field(w, table=table)
+    J, g = oracle.objective(w, H)
+    ob = oracle.objective_box(w)
+    jm = oracle.objective_mask(w)
+    out = []
+    for (z, y, x) in cells:
+        A = oracle.field(w.n, w.h, g, ob, (x, x + 1, y, y + 1, z, z + 1), jm, oracle.m0_mask(w), table)
+        out.append(oracle.gradient_from_adjoint(w, A)[z, y, x])
+    return J, np.array(out)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gpu_full_size_256x256x128_sampled(torch, dtype):
+    """The benchmark workload (256 x 256 x 128, padded 512 x 512 x 256) in
+    the benchmark's launch configuration: J exactly, and the gradient on the
+    whole top design layer under the sensor (where it is largest) plus random
+    design cells, against the oracle's direct sums."""
+    w = wl.config3()
+    say("full size", dtype)
+    e = tof().engine_for(w, dtype)
+    assert e.padded_lengths() == (512, 512, 256)
+    J, g = e.objective_and_grad(dev(torch, w.rho, e.dtype))
+    torch.cuda.synchronize()
+    g = host(g)
+    rng = np.random.default_rng(3)
+    top = w.design[5] - 1
+    cells = [(top, y, x) for y in range(94, 162, 4) for x in range(94, 162, 4)]
+    cells += [(int(rng.integers(0, 124)), int(rng.integers(0, 256)), int(rng.integers(0, 256))) for _ in range(64)]
+    Jr, gr = sampled_reference(w, cells)
+    got = np.array([g[c] for c in cells])
+    assert abs(float(J.item()) - Jr) <= TOL[dtype] * abs(Jr)
+    assert np.abs(got - gr).max() <= TOL[dtype] * np.abs(gr).max()
+    assert np.all(g[124:] == 0.0)
