@@ -211,11 +211,16 @@ int comp_of(int a, int b)
 void finish_product(ProductDev &pr)
 {
     pr.need = 0;
+    std::memset(pr.W, 0, sizeof(pr.W));
     for (int o = 0; o < pr.c_out; ++o)
         for (int i = 0; i < pr.c_in; ++i)
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b)
-                    if (pr.U[o][a] != 0.0 && pr.V[b][i] != 0.0) pr.need |= 1 << comp_of(a, b);
+                    if (pr.U[o][a] != 0.0 && pr.V[b][i] != 0.0) {
+                        const int c = comp_of(a, b);
+                        pr.need |= 1 << c;
+                        pr.W[o][i][c] += pr.U[o][a] * pr.V[b][i];
+                    }
 }
 
 // ---- one convolution: five passes ----

@@ -48,9 +48,10 @@ struct View4 {
 // C = U K V, K the 3x3 symmetric tensor spectrum at the frequency.
 struct ProductDev {
     int c_in, c_out;
-    double U[3][3];   // [o][a]
-    double V[3][3];   // [b][i]
-    int need;         // bit mask of tensor components (xx, yy, zz, xy, xz, yz) to load
+    double U[3][3];     // [o][a]
+    double V[3][3];     // [b][i]
+    double W[3][3][6];  // [o][i][c]: C_oi = sum_c W[o][i][c] K_c (U and V folded per component)
+    int need;           // bit mask of tensor components (xx, yy, zz, xy, xz, yz) to load
 };
 
 // Octant-compressed real tensor spectra, [6][hx][Lz/2+1][ky_pitch].

@@ -17,6 +17,7 @@
 
 #include "dd.h"
 #include "engine.h"
+#include "fft_reg.h"
 
 namespace {
 
@@ -588,6 +589,297 @@ __global__ __launch_bounds__(kThreads) void k_extract_spectrum(const cplx<double
     atomicMax(mx_real, (unsigned long long)__double_as_longlong(mr));
 }
 
+// ===========================================================================
+// Register-resident variants for power-of-two lengths fixed at compile time.
+// Same passes, layouts and epilogues as above; thread p of a line holds
+// x[p + P m] (see fft_reg.h).
+
+// -- passes 2 and 4: contiguous lines --------------------------------------
+template <typename R, int L, int E, int NL>
+__global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cplx<R> *out, int nlines, int inner,
+                                                        long long in_outer, long long in_inner, long long out_outer,
+                                                        long long out_inner, int p_in, int n_in, int p_out,
+                                                        int n_out, const cplx<R> *table, int inv)
+{
+    constexpr int P = L / E;
+    constexpr int PITCH = regfft::padded_len(L);
+    constexpr int NT = regfft::twiddle_count(L, E);
+    __shared__ cplx<R> lds[NL * PITCH];
+    const int l = threadIdx.x / P;
+    const int p = threadIdx.x % P;
+    const int line = blockIdx.x * NL + l;
+    const bool live = line < nlines;
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    cplx<R> v[E];
+    const long long ib = (long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner - p_in;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int n = p + P * m;
+        v[m] = (live && n >= p_in && n < p_in + n_in) ? in[ib + n] : cplx<R>{0, 0};
+    }
+    regfft::fft_line<R, L, E>(v, tw, lds + l * PITCH, p, inv != 0);
+    if (live) {
+        const long long ob = (long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner - p_out;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int n = p + P * m;
+            if (n >= p_out && n < p_out + n_out) out[ob + n] = v[m];
+        }
+    }
+}
+
+// -- pass 3: z FFT, tensor product, inverse z --------------------------------
+// Block: TKC consecutive ky columns of one kx; lanes run over the columns so
+// every row access is TKC contiguous complex values.
+template <typename R, int L, int E, int TKC, int CI, int CO>
+__global__ __launch_bounds__(TKC *(L / E)) void k_z_reg(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
+                                                      int zt0, int nzt, SpectrumDev<R> spec, ProductDev prod,
+                                                      const cplx<R> *table)
+{
+    constexpr int P = L / E;
+    constexpr int PITCH = regfft::padded_len(L) + 1;   // odd: columns start on different banks
+    constexpr int NT = regfft::twiddle_count(L, E);
+    __shared__ cplx<R> lds[TKC * PITCH];
+    const int col = threadIdx.x % TKC;
+    const int p = threadIdx.x / TKC;
+    const int kx = blockIdx.y;
+    const int ky = blockIdx.x * TKC + col;
+    const bool live = ky < Ly;
+    const long long cstride = (long long)hx * Zrows * Ly;
+    cplx<R> *colp = B + (long long)kx * Zrows * Ly + (live ? ky : 0);
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    cplx<R> *my = lds + col * PITCH;
+
+    cplx<R> X[CI][E];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int n = p + P * m;
+            X[i][m] = (live && n >= zs0 && n < zs0 + nzs) ? colp[i * cstride + (long long)(n - zs0) * Ly]
+                                                          : cplx<R>{0, 0};
+        }
+        regfft::fft_line<R, L, E>(X[i], tw, my, p, false);
+    }
+    // per-frequency product: C_oi = sum_c W[o][i][c] K_c(kx, ky, kz)
+    const int hLy = Ly / 2;
+    const int kyq = ky <= hLy ? ky : Ly - ky;
+    const R sy = ky > hLy ? (R)-1 : (R)1;
+    R Wc[CO][CI][6];
+#pragma unroll
+    for (int o = 0; o < CO; ++o)
+#pragma unroll
+        for (int i = 0; i < CI; ++i)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) Wc[o][i][c] = (R)prod.W[o][i][c];
+    cplx<R> Y[CO][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int kz = p + P * m;
+        const int kzq = kz <= L / 2 ? kz : L - kz;
+        const R sz = kz > L / 2 ? (R)-1 : (R)1;
+        R K[6];
+        const long long at = ((long long)kx * spec.hkz + kzq) * spec.ky_pitch + (live ? kyq : 0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) K[c] = (prod.need >> c & 1) ? spec.k[c * spec.comp_stride + at] : (R)0;
+        K[3] *= sy;        // xy: odd in y
+        K[4] *= sz;        // xz: odd in z
+        K[5] *= sy * sz;   // yz: odd in y and z
+#pragma unroll
+        for (int o = 0; o < CO; ++o) {
+            cplx<R> acc{0, 0};
+#pragma unroll
+            for (int i = 0; i < CI; ++i) {
+                R coef = 0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) coef += Wc[o][i][c] * K[c];
+                acc.x += coef * X[i][m].x;
+                acc.y += coef * X[i][m].y;
+            }
+            Y[o][m] = acc;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+        regfft::fft_line<R, L, E>(Y[o], tw, my, p, true);
+        if (live) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int n = p + P * m;
+                if (n >= zt0 && n < zt0 + nzt) colp[o * cstride + (long long)(n - zt0) * Ly] = Y[o][m];
+            }
+        }
+    }
+}
+
+// -- pass 1: real-to-complex FFT along x, transposed store ------------------
+// Block: NLC complex lines = 2 NLC source rows of one z (and one component).
+template <typename R, int L, int E, int NLC>
+__global__ __launch_bounds__(NLC *(L / E)) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src, Box S,
+                                                       cplx<R> *out, int hx, const cplx<R> *table)
+{
+    constexpr int P = L / E;
+    constexpr int TY = 2 * NLC;
+    constexpr int PITCH = regfft::padded_len(L);
+    constexpr int NT = regfft::twiddle_count(L, E);
+    __shared__ cplx<R> lds[NLC * PITCH];
+    const int l = threadIdx.x / P;
+    const int p = threadIdx.x % P;
+    const int c = blockIdx.z;
+    const int zrel = blockIdx.y;
+    const int z = S.z0 + zrel;
+    const int ybase = S.y0 + blockIdx.x * TY;
+    const int nrow = min(TY, S.y1 - ybase);
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    cplx<R> v[E];
+    const int r0 = 2 * l;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = p + P * m;
+        R re = 0, im = 0;
+        if (x >= S.x0 && x < S.x1) {
+            if (r0 < nrow) re = source_value(mode, dsg, src, c, x, ybase + r0, z);
+            if (r0 + 1 < nrow) im = source_value(mode, dsg, src, c, x, ybase + r0 + 1, z);
+        }
+        v[m] = cplx<R>{re, im};
+    }
+    cplx<R> *my = lds + l * PITCH;
+    regfft::fft_line<R, L, E>(v, tw, my, p, false);
+    // natural-order spectrum of every line into LDS, then split the pairs
+#pragma unroll
+    for (int m = 0; m < E; ++m) my[regfft::swz(p + P * m)] = v[m];
+    __syncthreads();
+    const int nys = S.ny(), nzs = S.nz();
+    const long long kxs = (long long)nzs * nys;
+    cplx<R> *o = out + (long long)c * hx * kxs + (long long)zrel * nys + (ybase - S.y0);
+    const R half = (R)0.5;
+    for (int e = threadIdx.x; e < hx * TY; e += blockDim.x) {
+        const int k = e / TY;
+        const int r = e % TY;
+        if (r >= nrow) continue;
+        const cplx<R> *line = lds + (r >> 1) * PITCH;
+        const cplx<R> Zk = line[regfft::swz(k)];
+        const cplx<R> Zm = line[regfft::swz((L - k) & (L - 1))];
+        cplx<R> w;
+        if ((r & 1) == 0) w = cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half};
+        else w = cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
+        o[k * kxs + r] = w;
+    }
+}
+
+// -- pass 5: complex-to-real inverse FFT along x + epilogue -----------------
+// Block: NLC complex lines = 2 NLC target rows of one z, all CO components.
+template <typename R, int L, int E, int NLC, int CO>
+__global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi, View4<R> out,
+                                                       DesignDev<R> dsg, R m0u0, R m0u1, R m0u2, R *grad,
+                                                       const cplx<R> *table)
+{
+    constexpr int P = L / E;
+    constexpr int TY = 2 * NLC;
+    constexpr int PITCH = regfft::padded_len(L);
+    constexpr int HX = L / 2 + 1;
+    constexpr int NT = regfft::twiddle_count(L, E);
+    constexpr int NLDS = TY * HX > NLC * PITCH ? TY * HX : NLC * PITCH;   // staging or exchange
+    __shared__ cplx<R> lds[NLDS];
+    const int l = threadIdx.x / P;
+    const int p = threadIdx.x % P;
+    const int zrel = blockIdx.y;
+    const int z = T.z0 + zrel;
+    const int ybase = T.y0 + blockIdx.x * TY;
+    const int nrow = min(TY, T.y1 - ybase);
+    const int nyt = T.ny(), nzt = T.nz();
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    const int rA = 2 * l, rB = 2 * l + 1;
+    const R m0u[3] = {m0u0, m0u1, m0u2};
+    const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
+    R acc[2][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) acc[0][m] = acc[1][m] = 0;
+#pragma unroll
+    for (int cc = 0; cc < CO; ++cc) {
+        // stage the half spectra of the TY rows as [r][k]
+        for (int e = threadIdx.x; e < HX * TY; e += blockDim.x) {
+            const int r = e % TY;
+            const int k = e / TY;
+            lds[r * HX + k] = r < nrow ? C[((long long)(cc * hx + k) * nzt + zrel) * nyt + (ybase - T.y0 + r)]
+                                       : cplx<R>{0, 0};
+        }
+        __syncthreads();
+        cplx<R> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int k = p + P * m;
+            cplx<R> a, b;
+            if (k <= L / 2) {
+                a = lds[rA * HX + k];
+                b = lds[rB * HX + k];
+                if (k == 0 || k == L / 2) {
+                    a.y = 0;
+                    b.y = 0;
+                }
+            } else {
+                a = cconj(lds[rA * HX + (L - k)]);
+                b = cconj(lds[rB * HX + (L - k)]);
+            }
+            v[m] = cplx<R>{a.x - b.y, a.y + b.x};
+        }
+        __syncthreads();
+        regfft::fft_line<R, L, E>(v, tw, lds + l * PITCH, p, true);
+        __syncthreads();   // the next component restages into the same LDS
+        if (!grad_epi) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int x = p + P * m;
+                if (x < T.x0 || x >= T.x1) continue;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = 2 * l + h;
+                    if (r >= nrow) continue;
+                    const int y = ybase + r;
+                    out.ptr[cc * out.cs + (long long)(z - out.oz) * out.zs + (long long)(y - out.oy) * out.ys +
+                            (x - out.ox)] = h ? v[m].y : v[m].x;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int x = p + P * m;
+                if (x >= dsg.nx) continue;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int y = ybase + 2 * l + h;
+                    const R a = h ? v[m].y : v[m].x;
+                    const R coef = dsg.m0f ? dsg.m0f[cc * ncell + ((long long)z * dsg.ny + min(y, dsg.ny - 1)) * dsg.nx + x]
+                                           : m0u[cc];
+                    acc[h][m] += coef * a;
+                }
+            }
+        }
+    }
+    if (grad_epi) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int x = p + P * m;
+            if (x >= dsg.nx) continue;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int r = 2 * l + h;
+                if (r >= nrow) continue;
+                const int y = ybase + r;
+                const long long idx = ((long long)z * dsg.ny + y) * dsg.nx + x;
+                R g = 0;
+                if (x >= T.x0 && x < T.x1 && dsg.design.has(x, y, z) && (!dsg.mask || dsg.mask[idx]))
+                    g = (R)dsg.p * ipow_dev(dsg.rho[idx], dsg.p - 1) * acc[h][m];
+                grad[idx] = g;
+            }
+        }
+    }
+}
+
 // ---- launch configuration helpers ----
 
 constexpr size_t kLdsBudget = 64 * 1024;
@@ -605,10 +897,29 @@ hipError_t allow_lds(K kernel, size_t bytes)
 // ---------------------------------------------------------------------------
 // Launchers
 
+template <typename R, int L, int NLC>
+hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
+                         const FftPlanDev &plan, cplx<R> *out, int hx)
+{
+    constexpr int E = 8;
+    dim3 grid((S.ny() + 2 * NLC - 1) / (2 * NLC), S.nz(), c_in);
+    hipLaunchKernelGGL((k_xf_reg<R, L, E, NLC>), grid, dim3(NLC * (L / E)), 0, st, mode, dsg, src, S, out, hx,
+                       (const cplx<R> *)plan.tw);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
                             Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx)
 {
+    switch (plan.L) {
+    case 32: return launch_xf_reg<R, 32, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 64: return launch_xf_reg<R, 64, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 128: return launch_xf_reg<R, 128, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 256: return launch_xf_reg<R, 256, 8>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 512: return launch_xf_reg<R, 512, 8>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    default: break;
+    }
     const int L = plan.L;
     const int pitch = L + 1;
     const size_t per_line = 2 * (size_t)pitch * sizeof(cplx<R>);
@@ -623,6 +934,20 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
     return hipGetLastError();
 }
 
+template <typename R, int L>
+hipError_t launch_line_reg(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
+                           long long in_outer, long long in_inner, long long out_outer, long long out_inner,
+                           int p_in, int n_in, int p_out, int n_out, const FftPlanDev &plan, bool inv)
+{
+    constexpr int E = 8;
+    constexpr int NL = 256 / (L / E);
+    dim3 grid((nlines + NL - 1) / NL);
+    hipLaunchKernelGGL((k_line_reg<R, L, E, NL>), grid, dim3(256), 0, st, in, out, nlines, inner, in_outer,
+                       in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, (const cplx<R> *)plan.tw,
+                       inv ? 1 : 0);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
@@ -630,6 +955,19 @@ hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
                            const FftPlanDev &plan, bool inv)
 {
     if (nlines <= 0) return hipSuccess;
+#define TOF_LINE_CASE(LL)                                                                                    \
+    case LL:                                                                                                 \
+        return launch_line_reg<R, LL>(st, in, out, nlines, inner, in_outer, in_inner, out_outer, out_inner, \
+                                      p_in, n_in, p_out, n_out, plan, inv);
+    switch (plan.L) {
+        TOF_LINE_CASE(32)
+        TOF_LINE_CASE(64)
+        TOF_LINE_CASE(128)
+        TOF_LINE_CASE(256)
+        TOF_LINE_CASE(512)
+    default: break;
+    }
+#undef TOF_LINE_CASE
     const int pitch = plan.L + 1;
     const size_t per_line = 2 * (size_t)pitch * sizeof(cplx<R>);
     int NL = (int)(kLdsBudget / per_line);
@@ -644,11 +982,49 @@ hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
     return hipGetLastError();
 }
 
+template <typename R, int L, int E, int CI, int CO>
+hipError_t launch_z_reg(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
+                        const SpectrumDev<R> &spec, const ProductDev &prod, const FftPlanDev &plan)
+{
+    constexpr int P = L / E;
+    constexpr int TKC0 = sizeof(R) == 4 ? 32 : 16;
+    constexpr int TKC = TKC0 * P > 1024 ? 1024 / P : TKC0;
+    dim3 grid((Ly + TKC - 1) / TKC, hx);
+    hipLaunchKernelGGL((k_z_reg<R, L, E, TKC, CI, CO>), grid, dim3(TKC * P), 0, st, B, hx, Ly, Zrows, zs0, nzs, zt0,
+                       nzt, spec, prod, (const cplx<R> *)plan.tw);
+    return hipGetLastError();
+}
+
+template <typename R, int L, int E>
+hipError_t launch_z_reg_c(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
+                          const SpectrumDev<R> &spec, const ProductDev &prod, const FftPlanDev &plan)
+{
+    const int key = prod.c_in * 4 + prod.c_out;
+    switch (key) {
+    case 5: return launch_z_reg<R, L, E, 1, 1>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+    case 7: return launch_z_reg<R, L, E, 1, 3>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+    case 13: return launch_z_reg<R, L, E, 3, 1>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+    case 15: return launch_z_reg<R, L, E, 3, 3>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R>
 hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
                          int zt0, int nzt, const SpectrumDev<R> &spec, const ProductDev &prod,
                          bool forward_only, const FftPlanDev &plan)
 {
+    const bool regular = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
+    if (!forward_only && regular) {
+        switch (plan.L) {
+        case 32: return launch_z_reg_c<R, 32, 8>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+        case 64: return launch_z_reg_c<R, 64, 8>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+        case 128: return launch_z_reg_c<R, 128, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+        case 256: return launch_z_reg_c<R, 256, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+        case 512: return launch_z_reg_c<R, 512, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+        default: break;
+        }
+    }
     const int pitch = plan.L + 1;
     const int cmax = prod.c_in > prod.c_out ? prod.c_in : prod.c_out;
     const size_t per_col = 2 * (size_t)cmax * pitch * sizeof(cplx<R>);
@@ -663,11 +1039,38 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
     return hipGetLastError();
 }
 
+template <typename R, int L, int NLC>
+hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T, const FftPlanDev &plan,
+                         bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad)
+{
+    constexpr int E = 8;
+    dim3 grid((T.ny() + 2 * NLC - 1) / (2 * NLC), T.nz());
+    if (c == 1)
+        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, 1>), grid, dim3(NLC * (L / E)), 0, st, C, hx, T,
+                           grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
+    else if (c == 3)
+        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, 3>), grid, dim3(NLC * (L / E)), 0, st, C, hx, T,
+                           grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
                             const DesignDev<R> &dsg, const R *m0u, R *grad)
 {
+    if (c == 1 || c == 3) {
+        switch (plan.L) {
+        case 32: return launch_xi_reg<R, 32, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 64: return launch_xi_reg<R, 64, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 128: return launch_xi_reg<R, 128, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 256: return launch_xi_reg<R, 256, 8>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 512: return launch_xi_reg<R, 512, 8>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        default: break;
+        }
+    }
     const int pitch = plan.L + 2;
     const size_t per_line = 2 * (size_t)c * pitch * sizeof(cplx<R>);
     int TY = 2 * (int)(kLdsBudget / per_line);
