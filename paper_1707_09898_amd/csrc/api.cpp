@@ -50,16 +50,18 @@ struct tof_ctx {
     bool f64 = false;
     size_t wsize = 4;   // bytes per real
     Plan1D px, py, pz;
-    // spectra [6][hx][hkz][ky_pitch] of the working precision
-    DeviceBuf spec;
+    // spectra [6][hx][hkz][ky_pitch] and x-y transforms [6][hx][nz][ky_pitch], working precision
+    DeviceBuf spec, kt;
     int hkz = 0, ky_pitch = 0;
-    long long comp_stride = 0;
+    long long comp_stride = 0, comp_stride_kt = 0;
     // pass workspaces
     DeviceBuf A, B, C;
     int Zrows = 0;
+    BlockMap bmap{};   // layout of B: [c][kx][ky / KB][z][ky % KB]
     // objective buffers
     DeviceBuf Hs, G, Ht;
     DeviceBuf scratch64;
+    DeviceBuf partials, ticket;   // objective: per-block partial sums, completion counter (kept at 0)
     // design
     bool has_design = false;
     Box design{};
@@ -221,6 +223,15 @@ void finish_product(ProductDev &pr)
                         pr.need |= 1 << c;
                         pr.W[o][i][c] += pr.U[o][a] * pr.V[b][i];
                     }
+    pr.nc = 0;
+    std::memset(pr.Wq, 0, sizeof(pr.Wq));
+    for (int c = 0; c < 6; ++c)
+        if (pr.need >> c & 1) {
+            for (int o = 0; o < 3; ++o)
+                for (int i = 0; i < 3; ++i) pr.Wq[o][i][pr.nc] = pr.W[o][i][c];
+            pr.comp[pr.nc++] = c;
+        }
+    for (int q = pr.nc; q < 6; ++q) pr.comp[q] = 0;
 }
 
 // ---- one convolution: five passes ----
@@ -253,16 +264,29 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
     HIP_TRY(ctx, timed(ctx, st, slot0 + 0, src_bytes + a_elems * cw, [&] {
         return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx);
     }));
+    const BlockMap plain{30, 0, 0};
+    const BlockMap bm = ctx->bmap;
     HIP_TRY(ctx, timed(ctx, st, slot0 + 1, (a_elems + b_in) * cw, [&] {
         return launch_line_fft<R>(st, A, B, prod.c_in * hx * S.nz(), S.nz(), (long long)S.nz() * S.ny(), S.ny(),
-                                  (long long)Zr * Ly, Ly, S.y0, S.ny(), 0, Ly, ply, false);
+                                  (long long)Zr * Ly, bm.row, S.y0, S.ny(), 0, Ly, ply, false, plain, bm);
     }));
-    HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + spec_bytes, [&] {
-        return launch_z_pass<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), sp, prod, false, plz);
-    }));
+    const bool zsum_counts = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
+    if (zsum_counts && (S.nz() <= kZsumMaxRows || T.nz() <= kZsumMaxRows)) {
+        // few source or target rows: direct sum against the x-y transformed tensor
+        KtDev<R> kt{(const R *)ctx->kt.p, ctx->comp_stride_kt, ctx->nz, ctx->ky_pitch};
+        const int drows = std::min(ctx->nz, S.nz() + T.nz() - 1);
+        const double kt_bytes = ncomp * (double)hx * drows * (Ly / 2 + 1) * w;
+        HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + kt_bytes, [&] {
+            return launch_z_sum<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), kt, prod, bm);
+        }));
+    } else {
+        HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + spec_bytes, [&] {
+            return launch_z_pass<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), sp, prod, false, plz, bm);
+        }));
+    }
     HIP_TRY(ctx, timed(ctx, st, slot0 + 3, (b_out + c_elems) * cw, [&] {
-        return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)Zr * Ly, Ly,
-                                  (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true);
+        return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)Zr * Ly, bm.row,
+                                  (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true, bm, plain);
     }));
     HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
         return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad);
@@ -380,7 +404,7 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
     HIP_TRY(ctx, timed(ctx, st, 5, obytes, [&] {
         return launch_objective<R>(st, ctx->kind, (const R *)ctx->Hs.p, ob, ctx->sensor, cj, ctx->target, ctx->lam,
                                    ctx->dx, ctx->dy, ctx->dx * ctx->dy * ctx->dz, (const double *)ctx->Ht.p, J,
-                                   (R *)ctx->G.p);
+                                   (R *)ctx->G.p, (double *)ctx->partials.p, (unsigned int *)ctx->ticket.p);
     }));
     View4<const R> gsrc{(const R *)ctx->G.p, nob, (long long)ob.ny() * ob.nx(), ob.nx(), ob.x0, ob.y0, ob.z0};
     return adjoint_to_grad<R>(ctx, st, rho, gsrc, ob, jmask, grad);
@@ -423,11 +447,32 @@ tof_status compute_spectra(tof_ctx *ctx, hipStream_t st)
         HIP_TRY(ctx, launch_newell_stencil(st, c, nx, ny, nz, lx, ly, ctx->dx, ctx->dy, ctx->dz,
                                            (const double *)lat.p, (double *)W.p, Lx, Ly, Lz, nullptr));
         HIP_TRY(ctx, launch_x_forward<double>(st, SRC_ARRAY, nodsg, wsrc, whole, 1, plx, (cplx<double> *)A64.p, hx));
+        const BlockMap plain{30, 0, Ly};
         HIP_TRY(ctx, launch_line_fft<double>(st, (const cplx<double> *)A64.p, (cplx<double> *)B64.p, hx * Lz, Lz,
                                              (long long)Lz * Ly, Ly, (long long)Lz * Ly, Ly, 0, Ly, 0, Ly, ply,
-                                             false));
+                                             false, plain, plain));
+        // x-y transform at z offsets 0..nz-1: real for components even in x, imaginary for xz, yz
+        const bool imag = (c == 4 || c == 5);
+        const double scale2 = -1.0 / ((double)Lx * Ly);
+        if (ctx->f64)
+            HIP_TRY(ctx, launch_extract_kt<double>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, nz, scale2, imag,
+                                                   (double *)ctx->kt.p + c * ctx->comp_stride_kt, ctx->ky_pitch, mi, mr));
+        else
+            HIP_TRY(ctx, launch_extract_kt<float>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, nz, scale2, imag,
+                                                  (float *)ctx->kt.p + c * ctx->comp_stride_kt, ctx->ky_pitch, mi, mr));
+        {
+            unsigned long long hb[2];
+            HIP_TRY(ctx, hipMemcpyAsync(hb, bits.p, sizeof(hb), hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipStreamSynchronize(st));
+            double other, part;
+            std::memcpy(&other, &hb[0], 8);
+            std::memcpy(&part, &hb[1], 8);
+            if (!(other <= 1e-9 * part) && part > 0)
+                return fail(ctx, TOF_ERR_NUMERIC, "x-y tensor transform of component " + std::to_string(c) +
+                                                      " has the wrong phase (ratio " + std::to_string(other / part) + ")");
+        }
         HIP_TRY(ctx, launch_z_pass<double>(st, (cplx<double> *)B64.p, hx, Ly, Lz, 0, Lz, 0, Lz, nospec, fwd, true,
-                                           plz));
+                                           plz, plain));
         if (ctx->f64)
             HIP_TRY(ctx, launch_extract_spectrum<double>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, scale,
                                                          (double *)ctx->spec.p + c * ctx->comp_stride, ctx->hkz,
@@ -454,7 +499,8 @@ void release(tof_ctx *ctx)
 {
     for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
     ctx->prof_ev.clear();
-    DeviceBuf *bufs[] = {&ctx->spec, &ctx->A, &ctx->B, &ctx->C, &ctx->Hs, &ctx->G, &ctx->Ht, &ctx->scratch64};
+    DeviceBuf *bufs[] = {&ctx->spec, &ctx->kt, &ctx->A, &ctx->B, &ctx->C, &ctx->Hs, &ctx->G, &ctx->Ht,
+                         &ctx->scratch64, &ctx->partials, &ctx->ticket};
     for (DeviceBuf *b : bufs)
         if (b->p) {
             (void)hipFree(b->p);
@@ -522,13 +568,33 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
     ctx->hkz = L[2] / 2 + 1;
     ctx->ky_pitch = ((L[1] / 2 + 1) + 15) / 16 * 16;
     ctx->comp_stride = (long long)ctx->hx * ctx->hkz * ctx->ky_pitch;
+    ctx->comp_stride_kt = (long long)ctx->hx * g.nz * ctx->ky_pitch;
     if ((s = dev_alloc(ctx, ctx->spec, ctx->wsize * 6 * (size_t)ctx->comp_stride)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->kt, ctx->wsize * 6 * (size_t)ctx->comp_stride_kt)) != TOF_OK) return bail(s);
     ctx->Zrows = g.nz;
+    {
+        // ky-blocked B (KB columns of 256 bytes) when both the y and the z
+        // passes take the register path; plain [c][kx][z][ky] otherwise
+        auto pow2_fast = [](int v) { return v >= 32 && v <= 512 && (v & (v - 1)) == 0; };
+        const int KB = ctx->f64 ? 16 : TOF_KB32;
+        int kbs = 0;
+        while ((1 << kbs) < KB) ++kbs;
+        if (pow2_fast(L[1]) && pow2_fast(L[2]))
+            ctx->bmap = BlockMap{kbs, (long long)g.nz * KB, KB};
+        else
+            ctx->bmap = BlockMap{30, 0, L[1]};
+    }
     const size_t cw = 2 * ctx->wsize;   // complex bytes
     if ((s = dev_alloc(ctx, ctx->A, cw * 3 * (size_t)ctx->hx * g.nz * g.ny)) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->B, cw * 3 * (size_t)ctx->hx * g.nz * L[1])) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->C, cw * 3 * (size_t)ctx->hx * g.nz * g.ny)) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->scratch64, 64)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->partials, sizeof(double) * kObjMaxBlocks)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->ticket, 64)) != TOF_OK) return bail(s);
+    {
+        hipError_t e0 = hipMemsetAsync(ctx->ticket.p, 0, 64, st);
+        if (e0 != hipSuccess) return bail(hip_fail(ctx, e0, "hipMemsetAsync(ticket)"));
+    }
     if ((s = compute_spectra(ctx, st)) != TOF_OK) return bail(s);
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(hip_fail(ctx, e, "tensor setup"));
@@ -722,8 +788,8 @@ tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3])
 size_t tof_workspace_bytes(const tof_ctx *ctx)
 {
     if (!ctx) return 0;
-    return ctx->spec.bytes + ctx->A.bytes + ctx->B.bytes + ctx->C.bytes + ctx->Hs.bytes + ctx->G.bytes +
-           ctx->Ht.bytes + ctx->scratch64.bytes;
+    return ctx->spec.bytes + ctx->kt.bytes + ctx->A.bytes + ctx->B.bytes + ctx->C.bytes + ctx->Hs.bytes + ctx->G.bytes +
+           ctx->Ht.bytes + ctx->scratch64.bytes + ctx->partials.bytes + ctx->ticket.bytes;
 }
 
 const char *tof_last_error(const tof_ctx *ctx)

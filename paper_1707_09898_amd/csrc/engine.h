@@ -18,6 +18,23 @@ struct Box {
     }
 };
 
+// ky-block width of the y-spectrum buffer in FP32 (FP64 uses 16): 256-byte rows
+#ifndef TOF_KB32
+#define TOF_KB32 32
+#endif
+
+// Element addressing of a ky line in the y-spectrum buffer B, which is
+// [c][kx][ky / KB][z][ky % KB] (KB = 2^s; KB = Ly, i.e. s large, is the plain
+// [c][kx][z][ky] layout).  Element q of a line is at blk * (q >> s) + (q & mask);
+// the element of column ky in row z is at col(ky, z).
+struct BlockMap {
+    int s;           // log2 KB
+    long long blk;   // elements between consecutive KB-blocks (Zrows * KB)
+    long long row;   // elements between consecutive z rows (KB)
+    __host__ __device__ long long at(int q) const { return blk * (q >> s) + (q & ((1 << s) - 1)); }
+    __host__ __device__ long long col(int ky, int z) const { return at(ky) + row * z; }
+};
+
 // Where the first (x) pass takes its source values from.
 enum SrcMode {
     SRC_RHO_SCALAR = 0,   // chi rho^p          (uniform M0 folded into the spectrum coefficients)
@@ -52,6 +69,9 @@ struct ProductDev {
     double V[3][3];     // [b][i]
     double W[3][3][6];  // [o][i][c]: C_oi = sum_c W[o][i][c] K_c (U and V folded per component)
     int need;           // bit mask of tensor components (xx, yy, zz, xy, xz, yz) to load
+    int nc;             // number of components in `need`
+    int comp[6];        // the needed components, in order
+    double Wq[3][3][6]; // [o][i][q] = W[o][i][comp[q]]
 };
 
 // Octant-compressed real tensor spectra, [6][hx][Lz/2+1][ky_pitch].
@@ -61,6 +81,23 @@ struct SpectrumDev {
     long long comp_stride;
     int hkz, ky_pitch;
 };
+
+// Tensor transformed along x and y only, per z offset d >= 0:
+// Kt_c(kx, ky, d) = -FFT2_xy(N_c)(kx, ky, d) / (Lx Ly), stored as
+// [6][hx][nz][ky_pitch] for |ky| <= Ly/2.  Components even in x (xx, yy, zz,
+// xy) are real; xz and yz (odd in x) are imaginary and stored as their
+// imaginary part.  Offsets of the other sign follow by parity (odd in y: xy,
+// yz; odd in z: xz, yz).  With it a z pass whose source or target is a few
+// rows becomes out(zt) = sum_zs Kt(zt - zs) x(zs) per (kx, ky) column.
+template <typename R>
+struct KtDev {
+    const R *k;
+    long long comp_stride;
+    int nzk, ky_pitch;
+};
+
+// rows below which the z pass sums against Kt instead of transforming
+constexpr int kZsumMaxRows = 4;
 
 // ---- host launchers (kernels.hip); all enqueue on `st` and return hipError_t ----
 
@@ -72,12 +109,22 @@ template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
                            long long out_inner, int p_in, int n_in, int p_out, int n_out,
-                           const FftPlanDev &plan, bool inv);
+                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout);
 
 template <typename R>
 hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
                          int zt0, int nzt, const SpectrumDev<R> &spec, const ProductDev &prod,
-                         bool forward_only, const FftPlanDev &plan);
+                         bool forward_only, const FftPlanDev &plan, BlockMap bm);
+
+// z pass as a direct sum against Kt; requires nzt <= kZsumMaxRows or nzs <= kZsumMaxRows
+template <typename R>
+hipError_t launch_z_sum(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
+                        const KtDev<R> &kt, const ProductDev &prod, BlockMap bm);
+
+template <typename R>
+hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Zb, int nz, double scale,
+                             bool imaginary, R *kt, int ky_pitch, unsigned long long *other_max_bits,
+                             unsigned long long *part_max_bits);
 
 template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
@@ -87,10 +134,13 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
 template <typename R>
 hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box keep);
 
+// blocks the objective kernel may use (partials buffer length)
+constexpr int kObjMaxBlocks = 1024;
+
 template <typename R>
 hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,
                             double target, double lam, double dx, double dy, double vcell,
-                            const double *h_target, double *J, R *g);
+                            const double *h_target, double *J, R *g, double *partials, unsigned int *ticket);
 
 template <typename R>
 hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, int nx, int ny, int nz,

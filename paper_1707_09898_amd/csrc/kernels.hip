@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_line_fft(const cplx<R> *in, cplx<R
                                                      int inner, long long in_outer, long long in_inner,
                                                      long long out_outer, long long out_inner, int p_in,
                                                      int n_in, int p_out, int n_out, FftPlanDev plan,
-                                                     int inv, int NL, int pitch)
+                                                     int inv, int NL, int pitch, BlockMap bin, BlockMap bout)
 {
     extern __shared__ unsigned char smem_raw[];
     cplx<R> *buf0 = reinterpret_cast<cplx<R> *>(smem_raw);
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_line_fft(const cplx<R> *in, cplx<R
         const int line = l0 + l;
         cplx<R> v{0, 0};
         if (pos >= p_in && pos < p_in + n_in)
-            v = in[(long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner + (pos - p_in)];
+            v = in[(long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner + bin.at(pos - p_in)];
         buf0[l * pitch + pos] = v;
     }
     __syncthreads();
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_line_fft(const cplx<R> *in, cplx<R
         const int l = e / n_out;
         const int q = e - l * n_out;
         const int line = l0 + l;
-        out[(long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner + q] =
+        out[(long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner + bout.at(q)] =
             res[l * pitch + p_out + q];
     }
 }
@@ -161,7 +161,7 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_z_pass(cplx<R> *B, int hx, int Ly, int Zrows, int zs0,
                                                    int nzs, int zt0, int nzt, SpectrumDev<R> spec,
                                                    ProductDev prod, int forward_only, FftPlanDev plan,
-                                                   int TK, int pitch)
+                                                   int TK, int pitch, BlockMap bm)
 {
     extern __shared__ unsigned char smem_raw[];
     const int cmax = max(prod.c_in, prod.c_out);
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_z_pass(cplx<R> *B, int hx, int Ly,
     const int k0 = blockIdx.x * TK;
     const int ncol = min(TK, Ly - k0);
     const long long cstride = (long long)hx * Zrows * Ly;
-    cplx<R> *base = B + (long long)kx * Zrows * Ly + k0;
+    cplx<R> *base = B + (long long)kx * Zrows * Ly;
     const int c_in = prod.c_in, c_out = prod.c_out;
     for (int e = threadIdx.x; e < c_in * L * TK; e += blockDim.x) {
         const int col = e % TK;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_z_pass(cplx<R> *B, int hx, int Ly,
         const int pos = rest % L;
         const int i = rest / L;
         cplx<R> v{0, 0};
-        if (col < ncol && pos >= zs0 && pos < zs0 + nzs) v = base[i * cstride + (long long)(pos - zs0) * Ly + col];
+        if (col < ncol && pos >= zs0 && pos < zs0 + nzs) v = base[i * cstride + bm.col(k0 + col, pos - zs0)];
         buf0[(i * TK + col) * pitch + pos] = v;
     }
     __syncthreads();
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_z_pass(cplx<R> *B, int hx, int Ly,
             const int rest = e / TK;
             const int pos = rest % L;
             const int i = rest / L;
-            if (col < ncol) base[i * cstride + (long long)pos * Ly + col] = res[(i * TK + col) * pitch + pos];
+            if (col < ncol) base[i * cstride + bm.col(k0 + col, pos)] = res[(i * TK + col) * pitch + pos];
         }
         return;
     }
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_z_pass(cplx<R> *B, int hx, int Ly,
         const int rest = e / TK;
         const int zq = rest % nzt;
         const int o = rest / nzt;
-        if (col < ncol) base[o * cstride + (long long)zq * Ly + col] = res2[(o * TK + col) * pitch + zt0 + zq];
+        if (col < ncol) base[o * cstride + bm.col(k0 + col, zq)] = res2[(o * TK + col) * pitch + zt0 + zq];
     }
 }
 
@@ -344,21 +344,36 @@ __global__ __launch_bounds__(kThreads) void k_x_inverse(const cplx<R> *C, int hx
     }
 }
 
+// Zero the x rows (y, z) outside keep.y x keep.z: first the whole layers with
+// z outside keep.z, then the rows of the kept layers with y outside keep.y.
+// Block b writes one row.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_zero_outside(R *a, int nx, int ny, int nz, Box keep)
 {
-    const int row = blockIdx.x;
-    const int y = row % ny;
-    const int z = row / ny;
-    if (y >= keep.y0 && y < keep.y1 && z >= keep.z0 && z < keep.z1) return;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) a[(long long)row * nx + x] = (R)0;
+    const int b = blockIdx.x;
+    const int dz = keep.z1 - keep.z0, dy = keep.y1 - keep.y0;
+    const int n_layer_rows = (nz - dz) * ny;
+    int y, z;
+    if (b < n_layer_rows) {
+        const int l = b / ny;
+        y = b % ny;
+        z = l < keep.z0 ? l : keep.z1 + (l - keep.z0);
+    } else {
+        const int q = b - n_layer_rows;
+        const int oy = ny - dy;
+        z = keep.z0 + q / oy;
+        const int yy = q % oy;
+        y = yy < keep.y0 ? yy : keep.y1 + (yy - keep.y0);
+    }
+    R *row = a + ((long long)z * ny + y) * nx;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = (R)0;
 }
 
 // ---------------------------------------------------------------------------
 // Objective J(H) in FP64 with a fixed-order reduction (deterministic), and
 // g = dJ/dH (exact derivative of the discrete J) on the whole objective box.
 // Hs: [c_j][ob] dense (c_j = 1: Hz only; 3: Hx, Hy, Hz).
-constexpr int kObjThreads = 1024;
+constexpr int kObjThreads = 256;
 
 template <typename R>
 __device__ __forceinline__ double hval(const R *Hs, const Box &ob, int cc, int x, int y, int z)
@@ -379,15 +394,22 @@ __device__ __forceinline__ double dy_at(const R *Hs, const Box &ob, int x, int y
     return (hval(Hs, ob, 0, x, y + 1, z) - hval(Hs, ob, 0, x, y - 1, z)) / (2.0 * dy);
 }
 
+// Block b: g on its slice of the objective box, and a partial J over its
+// slice of the sensor cells (fixed-order tree in LDS).  The last block to
+// finish (ticket counter) adds the partials in block order, writes J and
+// re-arms the counter, so J is the same on every run.
 template <typename R>
 __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs, Box ob, Box sb, int c_j,
                                                          double t, double lam, double dx, double dy,
-                                                         double vcell, const double *ht, double *J, R *g)
+                                                         double vcell, const double *ht, double *J, R *g,
+                                                         double *partials, unsigned int *ticket)
 {
     __shared__ double red[kObjThreads];
+    __shared__ bool last;
     const int S = sb.nx() * sb.ny() * sb.nz();
+    const int nb = gridDim.x;
     double acc = 0.0;
-    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += nb * blockDim.x) {
         const int x = sb.x0 + s % sb.nx();
         const int y = sb.y0 + (s / sb.nx()) % sb.ny();
         const int z = sb.z0 + s / (sb.nx() * sb.ny());
@@ -415,11 +437,11 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && J) *J = (kind == 4) ? -0.5 * vcell * red[0] : red[0] / (double)S;
 
     const long long nob = (long long)ob.nx() * ob.ny() * ob.nz();
     const double invS = 1.0 / (double)S;
-    for (long long q = threadIdx.x; q < c_j * nob; q += blockDim.x) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < c_j * nob;
+         q += (long long)nb * blockDim.x) {
         const int cc = (int)(q / nob);
         const long long w = q % nob;
         const int x = ob.x0 + (int)(w % ob.nx());
@@ -447,6 +469,20 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
             }
         }
         g[q] = (R)v;
+    }
+
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = red[0];
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == (unsigned int)(nb - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        double total = 0.0;
+        for (int b = 0; b < nb; ++b) total += ((volatile double *)partials)[b];
+        if (J) *J = (kind == 4) ? -0.5 * vcell * total : total / (double)S;
+        *ticket = 0u;
     }
 }
 
@@ -599,7 +635,8 @@ template <typename R, int L, int E, int NL>
 __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                                                         long long in_outer, long long in_inner, long long out_outer,
                                                         long long out_inner, int p_in, int n_in, int p_out,
-                                                        int n_out, const cplx<R> *table, int inv)
+                                                        int n_out, const cplx<R> *table, int inv, BlockMap bin,
+                                                        BlockMap bout)
 {
     constexpr int P = L / E;
     constexpr int PITCH = regfft::padded_len(L);
@@ -612,34 +649,43 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
     cplx<R> v[E];
-    const long long ib = (long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner - p_in;
+    const long long ib = (long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int n = p + P * m;
-        v[m] = (live && n >= p_in && n < p_in + n_in) ? in[ib + n] : cplx<R>{0, 0};
+        v[m] = (live && n >= p_in && n < p_in + n_in) ? in[ib + bin.at(n - p_in)] : cplx<R>{0, 0};
     }
     regfft::fft_line<R, L, E>(v, tw, lds + l * PITCH, p, inv != 0);
     if (live) {
-        const long long ob = (long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner - p_out;
+        const long long ob = (long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int n = p + P * m;
-            if (n >= p_out && n < p_out + n_out) out[ob + n] = v[m];
+            if (n >= p_out && n < p_out + n_out) out[ob + bout.at(n - p_out)] = v[m];
         }
     }
 }
 
 // -- pass 3: z FFT, tensor product, inverse z --------------------------------
 // Block: TKC consecutive ky columns of one kx; lanes run over the columns so
-// every row access is TKC contiguous complex values.
-template <typename R, int L, int E, int TKC, int CI, int CO>
-__global__ __launch_bounds__(TKC *(L / E)) void k_z_reg(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
+// every row access is TKC contiguous complex values.  NC = number of tensor
+// components the product reads (1: a single projected component; 6: all,
+// with zero weights where unused).  A single source row skips the forward
+// FFT (its transform is a phase ramp); a single target row replaces the
+// inverse FFT by one inverse DFT sum per column.
+#ifndef TOF_Z_WAVES_PER_EU
+#define TOF_Z_WAVES_PER_EU 1
+#endif
+
+template <typename R, int L, int E, int TKC, int CI, int CO, int NC>
+__global__ __launch_bounds__(TKC *(L / E)) __attribute__((amdgpu_waves_per_eu(TOF_Z_WAVES_PER_EU))) void k_z_reg(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
                                                       int zt0, int nzt, SpectrumDev<R> spec, ProductDev prod,
-                                                      const cplx<R> *table)
+                                                      const cplx<R> *table, BlockMap bm)
 {
     constexpr int P = L / E;
     constexpr int PITCH = regfft::padded_len(L) + 1;   // odd: columns start on different banks
     constexpr int NT = regfft::twiddle_count(L, E);
+    static_assert(CO * P <= PITCH, "reduction area must fit");
     __shared__ cplx<R> lds[TKC * PITCH];
     const int col = threadIdx.x % TKC;
     const int p = threadIdx.x / TKC;
@@ -647,46 +693,58 @@ __global__ __launch_bounds__(TKC *(L / E)) void k_z_reg(cplx<R> *B, int hx, int 
     const int ky = blockIdx.x * TKC + col;
     const bool live = ky < Ly;
     const long long cstride = (long long)hx * Zrows * Ly;
-    cplx<R> *colp = B + (long long)kx * Zrows * Ly + (live ? ky : 0);
+    // this column's element of row z is colp[bm.row * z]
+    cplx<R> *colp = B + (long long)kx * Zrows * Ly + bm.col(live ? ky : 0, 0);
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
     cplx<R> *my = lds + col * PITCH;
 
-    cplx<R> X[CI][E];
-#pragma unroll
-    for (int i = 0; i < CI; ++i) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int n = p + P * m;
-            X[i][m] = (live && n >= zs0 && n < zs0 + nzs) ? colp[i * cstride + (long long)(n - zs0) * Ly]
-                                                          : cplx<R>{0, 0};
-        }
-        regfft::fft_line<R, L, E>(X[i], tw, my, p, false);
-    }
-    // per-frequency product: C_oi = sum_c W[o][i][c] K_c(kx, ky, kz)
+    // tensor spectrum at this thread's frequencies, fetched before the data
     const int hLy = Ly / 2;
-    const int kyq = ky <= hLy ? ky : Ly - ky;
+    const int kyq = live ? (ky <= hLy ? ky : Ly - ky) : 0;
     const R sy = ky > hLy ? (R)-1 : (R)1;
-    R Wc[CO][CI][6];
-#pragma unroll
-    for (int o = 0; o < CO; ++o)
-#pragma unroll
-        for (int i = 0; i < CI; ++i)
-#pragma unroll
-            for (int c = 0; c < 6; ++c) Wc[o][i][c] = (R)prod.W[o][i][c];
-    cplx<R> Y[CO][E];
+    R K[NC][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int kz = p + P * m;
         const int kzq = kz <= L / 2 ? kz : L - kz;
         const R sz = kz > L / 2 ? (R)-1 : (R)1;
-        R K[6];
-        const long long at = ((long long)kx * spec.hkz + kzq) * spec.ky_pitch + (live ? kyq : 0);
+        const long long at = ((long long)kx * spec.hkz + kzq) * spec.ky_pitch + kyq;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) K[c] = (prod.need >> c & 1) ? spec.k[c * spec.comp_stride + at] : (R)0;
-        K[3] *= sy;        // xy: odd in y
-        K[4] *= sz;        // xz: odd in z
-        K[5] *= sy * sz;   // yz: odd in y and z
+        for (int q = 0; q < NC; ++q) {
+            const int c = NC == 6 ? q : prod.comp[q];
+            R v = (NC < 6 || (prod.need >> c & 1)) ? spec.k[c * spec.comp_stride + at] : (R)0;
+            if (c == 3) v *= sy;             // xy: odd in y
+            else if (c == 4) v *= sz;        // xz: odd in z
+            else if (c == 5) v *= sy * sz;   // yz: odd in y and z
+            K[q][m] = v;
+        }
+    }
+
+    cplx<R> X[CI][E];
+    if (nzs == 1) {
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            const cplx<R> x = live ? colp[i * cstride] : cplx<R>{0, 0};
+#pragma unroll
+            for (int m = 0; m < E; ++m) X[i][m] = cmul(x, table[((p + P * m) * zs0) & (L - 1)]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int n = p + P * m;
+                X[i][m] = (live && n >= zs0 && n < zs0 + nzs) ? colp[i * cstride + (long long)(n - zs0) * bm.row]
+                                                              : cplx<R>{0, 0};
+            }
+            regfft::fft_line<R, L, E>(X[i], tw, my, p, false);
+        }
+    }
+    // per-frequency product: C_oi = sum_q Wq[o][i][q] K_q
+    cplx<R> Y[CO][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
 #pragma unroll
         for (int o = 0; o < CO; ++o) {
             cplx<R> acc{0, 0};
@@ -694,24 +752,207 @@ __global__ __launch_bounds__(TKC *(L / E)) void k_z_reg(cplx<R> *B, int hx, int 
             for (int i = 0; i < CI; ++i) {
                 R coef = 0;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) coef += Wc[o][i][c] * K[c];
+                for (int q = 0; q < NC; ++q) coef += (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q][m];
                 acc.x += coef * X[i][m].x;
                 acc.y += coef * X[i][m].y;
             }
             Y[o][m] = acc;
         }
     }
+    if (nzt == 1) {
+        // one target row: inverse DFT at z = zt0, summed over the column's P threads
 #pragma unroll
-    for (int o = 0; o < CO; ++o) {
-        regfft::fft_line<R, L, E>(Y[o], tw, my, p, true);
-        if (live) {
+        for (int o = 0; o < CO; ++o) {
+            cplx<R> part{0, 0};
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int n = p + P * m;
-                if (n >= zt0 && n < zt0 + nzt) colp[o * cstride + (long long)(n - zt0) * Ly] = Y[o][m];
+            for (int m = 0; m < E; ++m) part = cadd(part, cmul(Y[o][m], cconj(table[((p + P * m) * zt0) & (L - 1)])));
+            my[o * P + p] = part;
+        }
+        __syncthreads();
+        if (p == 0 && live) {
+#pragma unroll
+            for (int o = 0; o < CO; ++o) {
+                cplx<R> sum{0, 0};
+                for (int q = 0; q < P; ++q) sum = cadd(sum, my[o * P + q]);
+                colp[o * cstride] = sum;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < CO; ++o) {
+            regfft::fft_line<R, L, E>(Y[o], tw, my, p, true);
+            if (live) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int n = p + P * m;
+                    if (n >= zt0 && n < zt0 + nzt) colp[o * cstride + (long long)(n - zt0) * bm.row] = Y[o][m];
+                }
             }
         }
     }
+}
+
+// -- pass 3 as a direct sum against Kt (few source or few target rows) ------
+// Column (kx, ky), rows in B relative to the source / target box.  Kt_q at
+// offset d = zt - zs, with the parity signs of its component; imaginary
+// components (xz, yz) multiply by i.
+template <typename R, int NC>
+__device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int kyq, R sy, int d,
+                                      cplx<R> *K)
+{
+    const int dq = d < 0 ? -d : d;
+    const R sd = d < 0 ? (R)-1 : (R)1;
+    const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + kyq;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        const int c = NC == 6 ? q : prod.comp[q];
+        R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
+        if (c == 3) v *= sy;             // xy: odd in y
+        else if (c == 4) v *= sd;        // xz: odd in z
+        else if (c == 5) v *= sy * sd;   // yz: odd in y and z
+        K[q] = (c == 4 || c == 5) ? cplx<R>{0, v} : cplx<R>{v, 0};
+    }
+}
+
+// out_o += sum_i (sum_q W[o][i][q] K_q) x_i
+template <typename R, int CI, int CO, int NC>
+__device__ __forceinline__ void zsum_mac(const ProductDev &prod, const cplx<R> *K, const cplx<R> *x, cplx<R> *out)
+{
+#pragma unroll
+    for (int o = 0; o < CO; ++o)
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            cplx<R> coef{0, 0};
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]);
+                coef.x += w * K[q].x;
+                coef.y += w * K[q].y;
+            }
+            out[o] = cadd(out[o], cmul(coef, x[i]));
+        }
+}
+
+// Few target rows: TH threads per column split the source rows; partial
+// sums are added in thread order through LDS.
+template <typename R, int TKC, int TH, int CI, int CO, int NC>
+__global__ __launch_bounds__(TKC *TH) void k_zsum_gather(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
+                                                       int zt0, int nzt, KtDev<R> kt, ProductDev prod, BlockMap bm)
+{
+    constexpr int NR = kZsumMaxRows;
+    __shared__ cplx<R> red[TH * CO * NR * TKC];
+    const int col = threadIdx.x % TKC;
+    const int t = threadIdx.x / TKC;
+    const int kx = blockIdx.y;
+    const int ky = blockIdx.x * TKC + col;
+    const bool live = ky < Ly;
+    const long long cstride = (long long)hx * Zrows * Ly;
+    cplx<R> *colp = B + (long long)kx * Zrows * Ly + bm.col(live ? ky : 0, 0);
+    const int hLy = Ly / 2;
+    const int kyq = live ? (ky <= hLy ? ky : Ly - ky) : 0;
+    const R sy = ky > hLy ? (R)-1 : (R)1;
+    cplx<R> acc[NR][CO];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int o = 0; o < CO; ++o) acc[r][o] = cplx<R>{0, 0};
+    if (live) {
+        for (int zr = t; zr < nzs; zr += TH) {
+            cplx<R> x[CI];
+#pragma unroll
+            for (int i = 0; i < CI; ++i) x[i] = colp[i * cstride + (long long)zr * bm.row];
+            const int zs = zs0 + zr;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= nzt) break;
+                cplx<R> K[NC];
+                kt_at<R, NC>(kt, prod, kx, kyq, sy, zt0 + r - zs, K);
+                zsum_mac<R, CI, CO, NC>(prod, K, x, acc[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int o = 0; o < CO; ++o) red[((t * CO + o) * NR + r) * TKC + col] = acc[r][o];
+    __syncthreads();
+    if (t == 0 && live) {
+        for (int r = 0; r < nzt; ++r)
+#pragma unroll
+            for (int o = 0; o < CO; ++o) {
+                cplx<R> sum{0, 0};
+                for (int u = 0; u < TH; ++u) sum = cadd(sum, red[((u * CO + o) * NR + r) * TKC + col]);
+                colp[o * cstride + (long long)r * bm.row] = sum;
+            }
+    }
+}
+
+// Few source rows: every thread reads them, then TH threads per column split
+// the target rows.  The barrier keeps the in-place writes after all reads.
+template <typename R, int TKC, int TH, int CI, int CO, int NC>
+__global__ __launch_bounds__(TKC *TH) void k_zsum_scatter(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
+                                                        int zt0, int nzt, KtDev<R> kt, ProductDev prod, BlockMap bm)
+{
+    constexpr int NR = kZsumMaxRows;
+    const int col = threadIdx.x % TKC;
+    const int t = threadIdx.x / TKC;
+    const int kx = blockIdx.y;
+    const int ky = blockIdx.x * TKC + col;
+    const bool live = ky < Ly;
+    const long long cstride = (long long)hx * Zrows * Ly;
+    cplx<R> *colp = B + (long long)kx * Zrows * Ly + bm.col(live ? ky : 0, 0);
+    const int hLy = Ly / 2;
+    const int kyq = live ? (ky <= hLy ? ky : Ly - ky) : 0;
+    const R sy = ky > hLy ? (R)-1 : (R)1;
+    cplx<R> x[NR][CI];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int i = 0; i < CI; ++i)
+            x[r][i] = (live && r < nzs) ? colp[i * cstride + (long long)r * bm.row] : cplx<R>{0, 0};
+    __syncthreads();
+    if (!live) return;
+    for (int zr = t; zr < nzt; zr += TH) {
+        const int zt = zt0 + zr;
+        cplx<R> out[CO];
+#pragma unroll
+        for (int o = 0; o < CO; ++o) out[o] = cplx<R>{0, 0};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r >= nzs) break;
+            cplx<R> K[NC];
+            kt_at<R, NC>(kt, prod, kx, kyq, sy, zt - (zs0 + r), K);
+            zsum_mac<R, CI, CO, NC>(prod, K, x[r], out);
+        }
+#pragma unroll
+        for (int o = 0; o < CO; ++o) colp[o * cstride + (long long)zr * bm.row] = out[o];
+    }
+}
+
+// Kt from the x-y transform of the wrapped tensor (B = [kx][Zb rows][ky], plain):
+// the real or imaginary part times `scale` for z offsets 0..nz-1, and the
+// largest |other part| and |part| (bits) for the setup self-check.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, int hx, int Ly, int Zb, int nz,
+                                                       double scale, int imaginary, R *kt, int ky_pitch,
+                                                       unsigned long long *mx_other, unsigned long long *mx_part)
+{
+    const int hky = Ly / 2 + 1;
+    const long long n = (long long)hx * nz * hky;
+    double mo = 0.0, mp = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int ky = (int)(q % hky);
+        const int d = (int)((q / hky) % nz);
+        const int kx = (int)(q / ((long long)hky * nz));
+        const cplx<double> v = B[((long long)kx * Zb + d) * Ly + ky];
+        const double part = imaginary ? v.y : v.x, other = imaginary ? v.x : v.y;
+        kt[((long long)kx * nz + d) * ky_pitch + ky] = (R)(scale * part);
+        mo = fmax(mo, fabs(other));
+        mp = fmax(mp, fabs(part));
+    }
+    atomicMax(mx_other, (unsigned long long)__double_as_longlong(mo));
+    atomicMax(mx_part, (unsigned long long)__double_as_longlong(mp));
 }
 
 // -- pass 1: real-to-complex FFT along x, transposed store ------------------
@@ -897,11 +1138,25 @@ hipError_t allow_lds(K kernel, size_t bytes)
 // ---------------------------------------------------------------------------
 // Launchers
 
+#ifndef TOF_X_NLC512
+#define TOF_X_NLC512 8
+#endif
+#ifndef TOF_X_NLC256
+#define TOF_X_NLC256 8
+#endif
+
 template <typename R, int L, int NLC>
 hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
                          const FftPlanDev &plan, cplx<R> *out, int hx)
 {
     constexpr int E = 8;
+    if ((long long)((S.ny() + 2 * NLC - 1) / (2 * NLC)) * S.nz() * c_in < 512) {
+        // few rows: one row pair per block
+        dim3 grid((S.ny() + 1) / 2, S.nz(), c_in);
+        hipLaunchKernelGGL((k_xf_reg<R, L, E, 1>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
+                           (const cplx<R> *)plan.tw);
+        return hipGetLastError();
+    }
     dim3 grid((S.ny() + 2 * NLC - 1) / (2 * NLC), S.nz(), c_in);
     hipLaunchKernelGGL((k_xf_reg<R, L, E, NLC>), grid, dim3(NLC * (L / E)), 0, st, mode, dsg, src, S, out, hx,
                        (const cplx<R> *)plan.tw);
@@ -916,8 +1171,8 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
     case 32: return launch_xf_reg<R, 32, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
     case 64: return launch_xf_reg<R, 64, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
     case 128: return launch_xf_reg<R, 128, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 256: return launch_xf_reg<R, 256, 8>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 512: return launch_xf_reg<R, 512, 8>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 256: return launch_xf_reg<R, 256, TOF_X_NLC256>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 512: return launch_xf_reg<R, 512, TOF_X_NLC512>(st, mode, dsg, src, S, c_in, plan, out, hx);
     default: break;
     }
     const int L = plan.L;
@@ -937,14 +1192,22 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
 template <typename R, int L>
 hipError_t launch_line_reg(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer, long long out_inner,
-                           int p_in, int n_in, int p_out, int n_out, const FftPlanDev &plan, bool inv)
+                           int p_in, int n_in, int p_out, int n_out, const FftPlanDev &plan, bool inv, BlockMap bin,
+                           BlockMap bout)
 {
     constexpr int E = 8;
     constexpr int NL = 256 / (L / E);
+    if (nlines < 2048) {
+        // few lines (the sensor plane): one line per block spreads them over more CUs
+        hipLaunchKernelGGL((k_line_reg<R, L, E, 1>), dim3(nlines), dim3(L / E), 0, st, in, out, nlines, inner,
+                           in_outer, in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out,
+                           (const cplx<R> *)plan.tw, inv ? 1 : 0, bin, bout);
+        return hipGetLastError();
+    }
     dim3 grid((nlines + NL - 1) / NL);
     hipLaunchKernelGGL((k_line_reg<R, L, E, NL>), grid, dim3(256), 0, st, in, out, nlines, inner, in_outer,
                        in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, (const cplx<R> *)plan.tw,
-                       inv ? 1 : 0);
+                       inv ? 1 : 0, bin, bout);
     return hipGetLastError();
 }
 
@@ -952,13 +1215,13 @@ template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
                            long long out_inner, int p_in, int n_in, int p_out, int n_out,
-                           const FftPlanDev &plan, bool inv)
+                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout)
 {
     if (nlines <= 0) return hipSuccess;
 #define TOF_LINE_CASE(LL)                                                                                    \
     case LL:                                                                                                 \
         return launch_line_reg<R, LL>(st, in, out, nlines, inner, in_outer, in_inner, out_outer, out_inner, \
-                                      p_in, n_in, p_out, n_out, plan, inv);
+                                      p_in, n_in, p_out, n_out, plan, inv, bin, bout);
     switch (plan.L) {
         TOF_LINE_CASE(32)
         TOF_LINE_CASE(64)
@@ -978,33 +1241,43 @@ hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
     dim3 grid((nlines + NL - 1) / NL);
     hipLaunchKernelGGL(k_line_fft<R>, grid, dim3(kThreads), lds, st, in, out, nlines, inner, in_outer,
                        in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, plan, inv ? 1 : 0, NL,
-                       pitch);
+                       pitch, bin, bout);
     return hipGetLastError();
 }
 
-template <typename R, int L, int E, int CI, int CO>
+#ifndef TOF_Z_TKC32
+#define TOF_Z_TKC32 TOF_KB32
+#endif
+#ifndef TOF_Z_TKC64
+#define TOF_Z_TKC64 16
+#endif
+
+template <typename R, int L, int E, int CI, int CO, int NC>
 hipError_t launch_z_reg(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
-                        const SpectrumDev<R> &spec, const ProductDev &prod, const FftPlanDev &plan)
+                        const SpectrumDev<R> &spec, const ProductDev &prod, const FftPlanDev &plan, BlockMap bm)
 {
     constexpr int P = L / E;
-    constexpr int TKC0 = sizeof(R) == 4 ? 32 : 16;
+    constexpr int TKC0 = sizeof(R) == 4 ? TOF_Z_TKC32 : TOF_Z_TKC64;
     constexpr int TKC = TKC0 * P > 1024 ? 1024 / P : TKC0;
+    if (bm.s < 30 && (1 << bm.s) != TKC) return hipErrorInvalidValue;   // a block must own one KB-block
     dim3 grid((Ly + TKC - 1) / TKC, hx);
-    hipLaunchKernelGGL((k_z_reg<R, L, E, TKC, CI, CO>), grid, dim3(TKC * P), 0, st, B, hx, Ly, Zrows, zs0, nzs, zt0,
-                       nzt, spec, prod, (const cplx<R> *)plan.tw);
+    hipLaunchKernelGGL((k_z_reg<R, L, E, TKC, CI, CO, NC>), grid, dim3(TKC * P), 0, st, B, hx, Ly, Zrows, zs0, nzs,
+                       zt0, nzt, spec, prod, (const cplx<R> *)plan.tw, bm);
     return hipGetLastError();
 }
 
 template <typename R, int L, int E>
 hipError_t launch_z_reg_c(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
-                          const SpectrumDev<R> &spec, const ProductDev &prod, const FftPlanDev &plan)
+                          const SpectrumDev<R> &spec, const ProductDev &prod, const FftPlanDev &plan, BlockMap bm)
 {
     const int key = prod.c_in * 4 + prod.c_out;
+    if (key == 5 && prod.nc == 1)
+        return launch_z_reg<R, L, E, 1, 1, 1>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
     switch (key) {
-    case 5: return launch_z_reg<R, L, E, 1, 1>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-    case 7: return launch_z_reg<R, L, E, 1, 3>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-    case 13: return launch_z_reg<R, L, E, 3, 1>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-    case 15: return launch_z_reg<R, L, E, 3, 3>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+    case 5: return launch_z_reg<R, L, E, 1, 1, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+    case 7: return launch_z_reg<R, L, E, 1, 3, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+    case 13: return launch_z_reg<R, L, E, 3, 1, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+    case 15: return launch_z_reg<R, L, E, 3, 3, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1012,16 +1285,16 @@ hipError_t launch_z_reg_c(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows,
 template <typename R>
 hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
                          int zt0, int nzt, const SpectrumDev<R> &spec, const ProductDev &prod,
-                         bool forward_only, const FftPlanDev &plan)
+                         bool forward_only, const FftPlanDev &plan, BlockMap bm)
 {
     const bool regular = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
     if (!forward_only && regular) {
         switch (plan.L) {
-        case 32: return launch_z_reg_c<R, 32, 8>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-        case 64: return launch_z_reg_c<R, 64, 8>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-        case 128: return launch_z_reg_c<R, 128, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-        case 256: return launch_z_reg_c<R, 256, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
-        case 512: return launch_z_reg_c<R, 512, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan);
+        case 32: return launch_z_reg_c<R, 32, 8>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+        case 64: return launch_z_reg_c<R, 64, 8>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+        case 128: return launch_z_reg_c<R, 128, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+        case 256: return launch_z_reg_c<R, 256, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
+        case 512: return launch_z_reg_c<R, 512, 16>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, spec, prod, plan, bm);
         default: break;
         }
     }
@@ -1035,7 +1308,7 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
     if (e != hipSuccess) return e;
     dim3 grid((Ly + TK - 1) / TK, hx);
     hipLaunchKernelGGL(k_z_pass<R>, grid, dim3(kThreads), lds, st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt,
-                       spec, prod, forward_only ? 1 : 0, plan, TK, pitch);
+                       spec, prod, forward_only ? 1 : 0, plan, TK, pitch, bm);
     return hipGetLastError();
 }
 
@@ -1044,6 +1317,8 @@ hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                          bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad)
 {
     constexpr int E = 8;
+    if ((long long)((T.ny() + 2 * NLC - 1) / (2 * NLC)) * T.nz() < 512 && NLC > 1)
+        return launch_xi_reg<R, L, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
     dim3 grid((T.ny() + 2 * NLC - 1) / (2 * NLC), T.nz());
     if (c == 1)
         hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, 1>), grid, dim3(NLC * (L / E)), 0, st, C, hx, T,
@@ -1066,8 +1341,8 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
         case 32: return launch_xi_reg<R, 32, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
         case 64: return launch_xi_reg<R, 64, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
         case 128: return launch_xi_reg<R, 128, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 256: return launch_xi_reg<R, 256, 8>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 512: return launch_xi_reg<R, 512, 8>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 256: return launch_xi_reg<R, 256, TOF_X_NLC256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 512: return launch_xi_reg<R, 512, TOF_X_NLC512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
         default: break;
         }
     }
@@ -1087,17 +1362,22 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
 template <typename R>
 hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box keep)
 {
-    hipLaunchKernelGGL(k_zero_outside<R>, dim3(ny * nz), dim3(kThreads), 0, st, a, nx, ny, nz, keep);
+    const int rows = (nz - keep.nz()) * ny + keep.nz() * (ny - keep.ny());
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_outside<R>, dim3(rows), dim3(kThreads), 0, st, a, nx, ny, nz, keep);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,
                             double target, double lam, double dx, double dy, double vcell,
-                            const double *h_target, double *J, R *g)
+                            const double *h_target, double *J, R *g, double *partials, unsigned int *ticket)
 {
-    hipLaunchKernelGGL(k_objective<R>, dim3(1), dim3(kObjThreads), 0, st, kind, Hs, ob, sensor, c_j,
-                       target, lam, dx, dy, vcell, h_target, J, g);
+    const long long work = (long long)c_j * ob.nx() * ob.ny() * ob.nz();
+    int nb = (int)((work + kObjThreads - 1) / kObjThreads);
+    nb = nb < 1 ? 1 : (nb > kObjMaxBlocks ? kObjMaxBlocks : nb);
+    hipLaunchKernelGGL(k_objective<R>, dim3(nb), dim3(kObjThreads), 0, st, kind, Hs, ob, sensor, c_j, target, lam,
+                       dx, dy, vcell, h_target, J, g, partials, ticket);
     return hipGetLastError();
 }
 
@@ -1154,23 +1434,78 @@ hipError_t launch_extract_spectrum(hipStream_t st, const cplx<double> *B, int hx
     return hipGetLastError();
 }
 
+template <typename R, int CI, int CO, int NC>
+hipError_t launch_zsum_t(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
+                         const KtDev<R> &kt, const ProductDev &prod, BlockMap bm)
+{
+    constexpr int TKC = sizeof(R) == 4 ? TOF_KB32 : 16;
+    constexpr int TH = 256 / TKC;
+    if (bm.s < 30 && (1 << bm.s) != TKC) return hipErrorInvalidValue;   // a block must own one KB-block
+    dim3 grid((Ly + TKC - 1) / TKC, hx);
+    if (nzt <= kZsumMaxRows)
+        hipLaunchKernelGGL((k_zsum_gather<R, TKC, TH, CI, CO, NC>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows, zs0,
+                           nzs, zt0, nzt, kt, prod, bm);
+    else if (nzs <= kZsumMaxRows)
+        hipLaunchKernelGGL((k_zsum_scatter<R, TKC, TH, CI, CO, NC>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
+                           zs0, nzs, zt0, nzt, kt, prod, bm);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_z_sum(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
+                        const KtDev<R> &kt, const ProductDev &prod, BlockMap bm)
+{
+    const int key = prod.c_in * 4 + prod.c_out;
+    if (key == 5 && prod.nc == 1)
+        return launch_zsum_t<R, 1, 1, 1>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
+    switch (key) {
+    case 5: return launch_zsum_t<R, 1, 1, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
+    case 7: return launch_zsum_t<R, 1, 3, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
+    case 13: return launch_zsum_t<R, 3, 1, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
+    case 15: return launch_zsum_t<R, 3, 3, 6>(st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Zb, int nz, double scale,
+                             bool imaginary, R *kt, int ky_pitch, unsigned long long *mo, unsigned long long *mp)
+{
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mo, 1);
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mp, 1);
+    const long long n = (long long)hx * nz * (Ly / 2 + 1);
+    int blocks = (int)((n + kThreads - 1) / kThreads);
+    blocks = blocks > 8192 ? 8192 : blocks;
+    hipLaunchKernelGGL(k_extract_kt<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Zb, nz, scale,
+                       imaginary ? 1 : 0, kt, ky_pitch, mo, mp);
+    return hipGetLastError();
+}
+
 #define TOF_INSTANTIATE(R)                                                                              \
     template hipError_t launch_x_forward<R>(hipStream_t, int, const DesignDev<R> &, View4<const R>, Box, \
                                             int, const FftPlanDev &, cplx<R> *, int);                    \
     template hipError_t launch_line_fft<R>(hipStream_t, const cplx<R> *, cplx<R> *, int, int, long long, \
                                            long long, long long, long long, int, int, int, int,          \
-                                           const FftPlanDev &, bool);                                    \
+                                           const FftPlanDev &, bool, BlockMap, BlockMap);                \
     template hipError_t launch_z_pass<R>(hipStream_t, cplx<R> *, int, int, int, int, int, int, int,     \
                                          const SpectrumDev<R> &, const ProductDev &, bool,               \
-                                         const FftPlanDev &);                                            \
+                                         const FftPlanDev &, BlockMap);                                  \
     template hipError_t launch_x_inverse<R>(hipStream_t, const cplx<R> *, int, int, Box,                 \
                                             const FftPlanDev &, bool, View4<R>, const DesignDev<R> &,    \
                                             const R *, R *);                                             \
     template hipError_t launch_zero_outside<R>(hipStream_t, R *, int, int, int, Box);                    \
     template hipError_t launch_objective<R>(hipStream_t, int, const R *, Box, Box, int, double, double,  \
-                                            double, double, double, const double *, double *, R *);      \
+                                            double, double, double, const double *, double *, R *,       \
+                                            double *, unsigned int *);                                   \
     template hipError_t launch_project_step<R>(hipStream_t, R *, const R *, int, int, int, Box, double,  \
                                                unsigned long long *);                                          \
+    template hipError_t launch_z_sum<R>(hipStream_t, cplx<R> *, int, int, int, int, int, int, int,       \
+                                        const KtDev<R> &, const ProductDev &, BlockMap);                 \
+    template hipError_t launch_extract_kt<R>(hipStream_t, const cplx<double> *, int, int, int, int, double, \
+                                             bool, R *, int, unsigned long long *,                      \
+                                             unsigned long long *);                                     \
     template hipError_t launch_extract_spectrum<R>(hipStream_t, const cplx<double> *, int, int, int,     \
                                                    double, R *, int, int, unsigned long long *,          \
                                                    unsigned long long *);
