@@ -625,6 +625,17 @@ __global__ __launch_bounds__(kThreads) void k_extract_spectrum(const cplx<double
     atomicMax(mx_real, (unsigned long long)__double_as_longlong(mr));
 }
 
+// Line index of the calling thread when P threads share a line.  With P a
+// multiple of the wave size every wave lies inside one line, so the index is
+// made wave-uniform (scalar registers: row pointers need no per-lane math).
+template <int P>
+__device__ __forceinline__ int line_of_thread()
+{
+    const int l = threadIdx.x / P;
+    if constexpr (P % 64 == 0) return __builtin_amdgcn_readfirstlane(l);
+    return l;
+}
+
 // ===========================================================================
 // Register-resident variants for power-of-two lengths fixed at compile time.
 // Same passes, layouts and epilogues as above; thread p of a line holds
@@ -642,7 +653,7 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
     constexpr int PITCH = regfft::padded_len(L);
     constexpr int NT = regfft::twiddle_count(L, E);
     __shared__ cplx<R> lds[NL * PITCH];
-    const int l = threadIdx.x / P;
+    const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
     const int line = blockIdx.x * NL + l;
     const bool live = line < nlines;
@@ -857,6 +868,7 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_gather(cplx<R> *B, int hx, int
 #pragma unroll
         for (int o = 0; o < CO; ++o) acc[r][o] = cplx<R>{0, 0};
     if (live) {
+#pragma unroll 4
         for (int zr = t; zr < nzs; zr += TH) {
             cplx<R> x[CI];
 #pragma unroll
@@ -966,7 +978,7 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xf_reg(int mode, DesignDev<R> 
     constexpr int PITCH = regfft::padded_len(L);
     constexpr int NT = regfft::twiddle_count(L, E);
     __shared__ cplx<R> lds[NLC * PITCH];
-    const int l = threadIdx.x / P;
+    const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
     const int c = blockIdx.z;
     const int zrel = blockIdx.y;
@@ -977,15 +989,41 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xf_reg(int mode, DesignDev<R> 
     regfft::load_twiddles<R, L, E>(table, p, tw);
     cplx<R> v[E];
     const int r0 = 2 * l;
+    // row-level facts once; per element only the x range remains
+    const int yA = ybase + r0, yB = yA + 1;
+    const bool okA = r0 < nrow, okB = r0 + 1 < nrow;
+    if (mode == SRC_ARRAY) {
+        const R *rowA = src.ptr + c * src.cs + (long long)(z - src.oz) * src.zs + (long long)(yA - src.oy) * src.ys - src.ox;
+        const R *rowB = rowA + src.ys;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int x = p + P * m;
-        R re = 0, im = 0;
-        if (x >= S.x0 && x < S.x1) {
-            if (r0 < nrow) re = source_value(mode, dsg, src, c, x, ybase + r0, z);
-            if (r0 + 1 < nrow) im = source_value(mode, dsg, src, c, x, ybase + r0 + 1, z);
+        for (int m = 0; m < E; ++m) {
+            const int x = p + P * m;
+            const bool in = x >= S.x0 && x < S.x1;
+            v[m] = cplx<R>{(in && okA) ? rowA[x] : (R)0, (in && okB) ? rowB[x] : (R)0};
         }
-        v[m] = cplx<R>{re, im};
+    } else {
+        const bool inA = okA && dsg.design.has(dsg.design.x0, yA, z);
+        const bool inB = okB && dsg.design.has(dsg.design.x0, yB, z);
+        const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
+        const long long offA = ((long long)z * dsg.ny + yA) * dsg.nx, offB = offA + dsg.nx;
+        const R *rhoA = dsg.rho + offA, *rhoB = dsg.rho + offB;
+        const int xl = max(S.x0, dsg.design.x0), xh = min(S.x1, dsg.design.x1);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int x = p + P * m;
+            const bool in = x >= xl && x < xh;
+            R a = (in && inA) ? ipow_dev(rhoA[x], dsg.p) : (R)0;
+            R b = (in && inB) ? ipow_dev(rhoB[x], dsg.p) : (R)0;
+            if (dsg.mask) {
+                if (in && inA && !dsg.mask[offA + x]) a = 0;
+                if (in && inB && !dsg.mask[offB + x]) b = 0;
+            }
+            if (mode == SRC_RHO_VECTOR) {
+                if (in && inA) a *= dsg.m0f[c * ncell + offA + x];
+                if (in && inB) b *= dsg.m0f[c * ncell + offB + x];
+            }
+            v[m] = cplx<R>{a, b};
+        }
     }
     cplx<R> *my = lds + l * PITCH;
     regfft::fft_line<R, L, E>(v, tw, my, p, false);
@@ -1025,7 +1063,7 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int h
     constexpr int NT = regfft::twiddle_count(L, E);
     constexpr int NLDS = TY * HX > NLC * PITCH ? TY * HX : NLC * PITCH;   // staging or exchange
     __shared__ cplx<R> lds[NLDS];
-    const int l = threadIdx.x / P;
+    const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
     const int zrel = blockIdx.y;
     const int z = T.z0 + zrel;
@@ -1085,37 +1123,45 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int h
                             (x - out.ox)] = h ? v[m].y : v[m].x;
                 }
             }
-        } else {
+        } else if (dsg.m0f) {
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const int x = p + P * m;
                 if (x >= dsg.nx) continue;
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int y = ybase + 2 * l + h;
-                    const R a = h ? v[m].y : v[m].x;
-                    const R coef = dsg.m0f ? dsg.m0f[cc * ncell + ((long long)z * dsg.ny + min(y, dsg.ny - 1)) * dsg.nx + x]
-                                           : m0u[cc];
-                    acc[h][m] += coef * a;
+                    const int y = min(ybase + 2 * l + h, dsg.ny - 1);
+                    acc[h][m] += dsg.m0f[cc * ncell + ((long long)z * dsg.ny + y) * dsg.nx + x] * (h ? v[m].y : v[m].x);
                 }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                acc[0][m] += m0u[cc] * v[m].x;
+                acc[1][m] += m0u[cc] * v[m].y;
             }
         }
     }
     if (grad_epi) {
+        // whole x rows: p rho^(p-1) acc inside the design region, zero elsewhere
+        const int xl = max(T.x0, dsg.design.x0), xh = min(T.x1, dsg.design.x1);
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int x = p + P * m;
-            if (x >= dsg.nx) continue;
+        for (int h = 0; h < 2; ++h) {
+            const int r = 2 * l + h;
+            if (r >= nrow) continue;
+            const int y = ybase + r;
+            const bool rowin = dsg.design.has(dsg.design.x0, y, z);
+            const long long off = ((long long)z * dsg.ny + y) * dsg.nx;
+            const R *rho = dsg.rho + off;
+            R *gr = grad + off;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = 2 * l + h;
-                if (r >= nrow) continue;
-                const int y = ybase + r;
-                const long long idx = ((long long)z * dsg.ny + y) * dsg.nx + x;
+            for (int m = 0; m < E; ++m) {
+                const int x = p + P * m;
+                if (x >= dsg.nx) continue;
                 R g = 0;
-                if (x >= T.x0 && x < T.x1 && dsg.design.has(x, y, z) && (!dsg.mask || dsg.mask[idx]))
-                    g = (R)dsg.p * ipow_dev(dsg.rho[idx], dsg.p - 1) * acc[h][m];
-                grad[idx] = g;
+                if (rowin && x >= xl && x < xh && (!dsg.mask || dsg.mask[off + x]))
+                    g = (R)dsg.p * ipow_dev(rho[x], dsg.p - 1) * acc[h][m];
+                gr[x] = g;
             }
         }
     }
