@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--f64-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB three times (a known-size kernel for "
+                         "calibrating memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -90,6 +93,15 @@ def main():
     from paper_1707_09898_amd import tof, workloads as wl
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copied {args.calibrate_copy_mib} MiB x3", file=sys.stderr, flush=True)
+        del a, b
     w = wl.config3()
     print(f"[bench] workload {w.name}, steps {args.steps}, warmup {args.warmup}", file=sys.stderr, flush=True)
 

@@ -52,7 +52,7 @@ struct tof_ctx {
     Plan1D px, py, pz;
     // spectra [6][hx][hkz][ky_pitch] and x-y transforms [6][hx][nz][ky_pitch], working precision
     DeviceBuf spec, kt;
-    int hkz = 0, ky_pitch = 0;
+    int hkz = 0, ky_pitch = 0, kt_pitch = 0;
     long long comp_stride = 0, comp_stride_kt = 0;
     // pass workspaces
     DeviceBuf A, B, C;
@@ -273,9 +273,9 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
     const bool zsum_counts = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
     if (zsum_counts && (S.nz() <= kZsumMaxRows || T.nz() <= kZsumMaxRows)) {
         // few source or target rows: direct sum against the x-y transformed tensor
-        KtDev<R> kt{(const R *)ctx->kt.p, ctx->comp_stride_kt, ctx->nz, ctx->ky_pitch};
+        KtDev<R> kt{(const R *)ctx->kt.p, ctx->comp_stride_kt, ctx->nz, ctx->kt_pitch};
         const int drows = std::min(ctx->nz, S.nz() + T.nz() - 1);
-        const double kt_bytes = ncomp * (double)hx * drows * (Ly / 2 + 1) * w;
+        const double kt_bytes = ncomp * (double)hx * drows * Ly * w;
         HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + kt_bytes, [&] {
             return launch_z_sum<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), kt, prod, bm);
         }));
@@ -456,10 +456,10 @@ tof_status compute_spectra(tof_ctx *ctx, hipStream_t st)
         const double scale2 = -1.0 / ((double)Lx * Ly);
         if (ctx->f64)
             HIP_TRY(ctx, launch_extract_kt<double>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, nz, scale2, imag,
-                                                   (double *)ctx->kt.p + c * ctx->comp_stride_kt, ctx->ky_pitch, mi, mr));
+                                                   (double *)ctx->kt.p + c * ctx->comp_stride_kt, ctx->kt_pitch, mi, mr));
         else
             HIP_TRY(ctx, launch_extract_kt<float>(st, (const cplx<double> *)B64.p, hx, Ly, Lz, nz, scale2, imag,
-                                                  (float *)ctx->kt.p + c * ctx->comp_stride_kt, ctx->ky_pitch, mi, mr));
+                                                  (float *)ctx->kt.p + c * ctx->comp_stride_kt, ctx->kt_pitch, mi, mr));
         {
             unsigned long long hb[2];
             HIP_TRY(ctx, hipMemcpyAsync(hb, bits.p, sizeof(hb), hipMemcpyDeviceToHost, st));
@@ -568,7 +568,8 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
     ctx->hkz = L[2] / 2 + 1;
     ctx->ky_pitch = ((L[1] / 2 + 1) + 15) / 16 * 16;
     ctx->comp_stride = (long long)ctx->hx * ctx->hkz * ctx->ky_pitch;
-    ctx->comp_stride_kt = (long long)ctx->hx * g.nz * ctx->ky_pitch;
+    ctx->kt_pitch = (L[1] + 31) / 32 * 32;
+    ctx->comp_stride_kt = (long long)ctx->hx * g.nz * ctx->kt_pitch;
     if ((s = dev_alloc(ctx, ctx->spec, ctx->wsize * 6 * (size_t)ctx->comp_stride)) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->kt, ctx->wsize * 6 * (size_t)ctx->comp_stride_kt)) != TOF_OK) return bail(s);
     ctx->Zrows = g.nz;

@@ -84,11 +84,11 @@ struct SpectrumDev {
 
 // Tensor transformed along x and y only, per z offset d >= 0:
 // Kt_c(kx, ky, d) = -FFT2_xy(N_c)(kx, ky, d) / (Lx Ly), stored as
-// [6][hx][nz][ky_pitch] for |ky| <= Ly/2.  Components even in x (xx, yy, zz,
-// xy) are real; xz and yz (odd in x) are imaginary and stored as their
-// imaginary part.  Offsets of the other sign follow by parity (odd in y: xy,
-// yz; odd in z: xz, yz).  With it a z pass whose source or target is a few
-// rows becomes out(zt) = sum_zs Kt(zt - zs) x(zs) per (kx, ky) column.
+// [6][hx][nz][kt_pitch] over all ky in [0, Ly) (rows aligned to 128 bytes).
+// Components even in x (xx, yy, zz, xy) are real; xz and yz (odd in x) are
+// imaginary and stored as their imaginary part.  Negative offsets follow by
+// parity in z (xz, yz are odd).  With it a z pass whose source or target is
+// a few rows becomes out(zt) = sum_zs Kt(zt - zs) x(zs) per (kx, ky) column.
 template <typename R>
 struct KtDev {
     const R *k;

@@ -19,6 +19,13 @@
 #include "engine.h"
 #include "fft_reg.h"
 
+#ifndef TOF_ZSUM_U
+#define TOF_ZSUM_U 4
+#endif
+#ifndef TOF_ZSUM_THREADS
+#define TOF_ZSUM_THREADS 256
+#endif
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -808,49 +815,47 @@ __global__ __launch_bounds__(TKC *(L / E)) __attribute__((amdgpu_waves_per_eu(TO
 // offset d = zt - zs, with the parity signs of its component; imaginary
 // components (xz, yz) multiply by i.
 template <typename R, int NC>
-__device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int kyq, R sy, int d,
-                                      cplx<R> *K)
+__device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int ky, int d, R *K)
 {
     const int dq = d < 0 ? -d : d;
     const R sd = d < 0 ? (R)-1 : (R)1;
-    const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + kyq;
+    const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + ky;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const int c = NC == 6 ? q : prod.comp[q];
         R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
-        if (c == 3) v *= sy;             // xy: odd in y
-        else if (c == 4) v *= sd;        // xz: odd in z
-        else if (c == 5) v *= sy * sd;   // yz: odd in y and z
-        K[q] = (c == 4 || c == 5) ? cplx<R>{0, v} : cplx<R>{v, 0};
+        if (c == 4 || c == 5) v *= sd;   // xz, yz: odd in z
+        K[q] = v;
     }
 }
 
-// out_o += sum_i (sum_q W[o][i][q] K_q) x_i
+// out_o += sum_i (sum_q W[o][i][q] K_q) x_i; K_q is real, or imaginary
+// (the stored value times i) for the components odd in x (xz, yz).
 template <typename R, int CI, int CO, int NC>
-__device__ __forceinline__ void zsum_mac(const ProductDev &prod, const cplx<R> *K, const cplx<R> *x, cplx<R> *out)
+__device__ __forceinline__ void zsum_mac(const ProductDev &prod, const R *K, const cplx<R> *x, cplx<R> *out)
 {
 #pragma unroll
     for (int o = 0; o < CO; ++o)
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
-            cplx<R> coef{0, 0};
+            R cre = 0, cim = 0;
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
-                const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]);
-                coef.x += w * K[q].x;
-                coef.y += w * K[q].y;
+                const int c = NC == 6 ? q : prod.comp[q];
+                const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q];
+                if (c == 4 || c == 5) cim += w;
+                else cre += w;
             }
-            out[o] = cadd(out[o], cmul(coef, x[i]));
+            out[o] = cadd(out[o], cmul(cplx<R>{cre, cim}, x[i]));
         }
 }
 
 // Few target rows: TH threads per column split the source rows; partial
 // sums are added in thread order through LDS.
-template <typename R, int TKC, int TH, int CI, int CO, int NC>
+template <typename R, int TKC, int TH, int CI, int CO, int NC, int NR>
 __global__ __launch_bounds__(TKC *TH) void k_zsum_gather(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
                                                        int zt0, int nzt, KtDev<R> kt, ProductDev prod, BlockMap bm)
 {
-    constexpr int NR = kZsumMaxRows;
     __shared__ cplx<R> red[TH * CO * NR * TKC];
     const int col = threadIdx.x % TKC;
     const int t = threadIdx.x / TKC;
@@ -859,28 +864,39 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_gather(cplx<R> *B, int hx, int
     const bool live = ky < Ly;
     const long long cstride = (long long)hx * Zrows * Ly;
     cplx<R> *colp = B + (long long)kx * Zrows * Ly + bm.col(live ? ky : 0, 0);
-    const int hLy = Ly / 2;
-    const int kyq = live ? (ky <= hLy ? ky : Ly - ky) : 0;
-    const R sy = ky > hLy ? (R)-1 : (R)1;
+    const int kyl = live ? ky : 0;
     cplx<R> acc[NR][CO];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int o = 0; o < CO; ++o) acc[r][o] = cplx<R>{0, 0};
     if (live) {
-#pragma unroll 4
-        for (int zr = t; zr < nzs; zr += TH) {
-            cplx<R> x[CI];
+        // U source rows per round, their loads issued before the arithmetic
+        constexpr int U = TOF_ZSUM_U;
+        for (int zr0 = t; zr0 < nzs; zr0 += TH * U) {
+            cplx<R> x[U][CI];
+            R K[U][NR][NC];
 #pragma unroll
-            for (int i = 0; i < CI; ++i) x[i] = colp[i * cstride + (long long)zr * bm.row];
-            const int zs = zs0 + zr;
+            for (int u = 0; u < U; ++u) {
+                const int zr = zr0 + u * TH;
+                const bool ok = zr < nzs;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                if (r >= nzt) break;
-                cplx<R> K[NC];
-                kt_at<R, NC>(kt, prod, kx, kyq, sy, zt0 + r - zs, K);
-                zsum_mac<R, CI, CO, NC>(prod, K, x, acc[r]);
+                for (int i = 0; i < CI; ++i)
+                    x[u][i] = ok ? colp[i * cstride + (long long)zr * bm.row] : cplx<R>{0, 0};
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (r < nzt && ok) kt_at<R, NC>(kt, prod, kx, kyl, zt0 + r - (zs0 + zr), K[u][r]);
+                    else {
+#pragma unroll
+                        for (int q = 0; q < NC; ++q) K[u][r][q] = (R)0;
+                    }
+                }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    if (r < nzt) zsum_mac<R, CI, CO, NC>(prod, K[u][r], x[u], acc[r]);
         }
     }
 #pragma unroll
@@ -901,11 +917,10 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_gather(cplx<R> *B, int hx, int
 
 // Few source rows: every thread reads them, then TH threads per column split
 // the target rows.  The barrier keeps the in-place writes after all reads.
-template <typename R, int TKC, int TH, int CI, int CO, int NC>
+template <typename R, int TKC, int TH, int CI, int CO, int NC, int NR>
 __global__ __launch_bounds__(TKC *TH) void k_zsum_scatter(cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
                                                         int zt0, int nzt, KtDev<R> kt, ProductDev prod, BlockMap bm)
 {
-    constexpr int NR = kZsumMaxRows;
     const int col = threadIdx.x % TKC;
     const int t = threadIdx.x / TKC;
     const int kx = blockIdx.y;
@@ -913,9 +928,7 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_scatter(cplx<R> *B, int hx, in
     const bool live = ky < Ly;
     const long long cstride = (long long)hx * Zrows * Ly;
     cplx<R> *colp = B + (long long)kx * Zrows * Ly + bm.col(live ? ky : 0, 0);
-    const int hLy = Ly / 2;
-    const int kyq = live ? (ky <= hLy ? ky : Ly - ky) : 0;
-    const R sy = ky > hLy ? (R)-1 : (R)1;
+    const int kyl = live ? ky : 0;
     cplx<R> x[NR][CI];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -924,20 +937,36 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_scatter(cplx<R> *B, int hx, in
             x[r][i] = (live && r < nzs) ? colp[i * cstride + (long long)r * bm.row] : cplx<R>{0, 0};
     __syncthreads();
     if (!live) return;
-    for (int zr = t; zr < nzt; zr += TH) {
-        const int zt = zt0 + zr;
-        cplx<R> out[CO];
+    constexpr int U = CI * NC <= 2 ? 16 : 4;
+    for (int zr0 = t; zr0 < nzt; zr0 += TH * U) {
+        // tensor values of U target rows first, then the sums and stores
+        R K[U][NR][NC];
 #pragma unroll
-        for (int o = 0; o < CO; ++o) out[o] = cplx<R>{0, 0};
+        for (int u = 0; u < U; ++u) {
+            const int zt = zt0 + zr0 + u * TH;
+            const bool ok = zr0 + u * TH < nzt;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (r >= nzs) break;
-            cplx<R> K[NC];
-            kt_at<R, NC>(kt, prod, kx, kyq, sy, zt - (zs0 + r), K);
-            zsum_mac<R, CI, CO, NC>(prod, K, x[r], out);
+            for (int r = 0; r < NR; ++r) {
+                if (r < nzs && ok) kt_at<R, NC>(kt, prod, kx, kyl, zt - (zs0 + r), K[u][r]);
+                else {
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) K[u][r][q] = (R)0;
+                }
+            }
         }
 #pragma unroll
-        for (int o = 0; o < CO; ++o) colp[o * cstride + (long long)zr * bm.row] = out[o];
+        for (int u = 0; u < U; ++u) {
+            const int zr = zr0 + u * TH;
+            if (zr >= nzt) break;
+            cplx<R> out[CO];
+#pragma unroll
+            for (int o = 0; o < CO; ++o) out[o] = cplx<R>{0, 0};
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nzs) zsum_mac<R, CI, CO, NC>(prod, K[u][r], x[r], out);
+#pragma unroll
+            for (int o = 0; o < CO; ++o) colp[o * cstride + (long long)zr * bm.row] = out[o];
+        }
     }
 }
 
@@ -949,14 +978,13 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
                                                        double scale, int imaginary, R *kt, int ky_pitch,
                                                        unsigned long long *mx_other, unsigned long long *mx_part)
 {
-    const int hky = Ly / 2 + 1;
-    const long long n = (long long)hx * nz * hky;
+    const long long n = (long long)hx * nz * Ly;
     double mo = 0.0, mp = 0.0;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
-        const int ky = (int)(q % hky);
-        const int d = (int)((q / hky) % nz);
-        const int kx = (int)(q / ((long long)hky * nz));
+        const int ky = (int)(q % Ly);
+        const int d = (int)((q / Ly) % nz);
+        const int kx = (int)(q / ((long long)Ly * nz));
         const cplx<double> v = B[((long long)kx * Zb + d) * Ly + ky];
         const double part = imaginary ? v.y : v.x, other = imaginary ? v.x : v.y;
         kt[((long long)kx * nz + d) * ky_pitch + ky] = (R)(scale * part);
@@ -1485,15 +1513,22 @@ hipError_t launch_zsum_t(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
                          const KtDev<R> &kt, const ProductDev &prod, BlockMap bm)
 {
     constexpr int TKC = sizeof(R) == 4 ? TOF_KB32 : 16;
-    constexpr int TH = 256 / TKC;
+    constexpr int TH = TOF_ZSUM_THREADS / TKC;
     if (bm.s < 30 && (1 << bm.s) != TKC) return hipErrorInvalidValue;   // a block must own one KB-block
     dim3 grid((Ly + TKC - 1) / TKC, hx);
-    if (nzt <= kZsumMaxRows)
-        hipLaunchKernelGGL((k_zsum_gather<R, TKC, TH, CI, CO, NC>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows, zs0,
-                           nzs, zt0, nzt, kt, prod, bm);
-    else if (nzs <= kZsumMaxRows)
-        hipLaunchKernelGGL((k_zsum_scatter<R, TKC, TH, CI, CO, NC>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
+    constexpr int NRM = kZsumMaxRows;
+    if (nzt == 1)
+        hipLaunchKernelGGL((k_zsum_gather<R, TKC, TH, CI, CO, NC, 1>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
                            zs0, nzs, zt0, nzt, kt, prod, bm);
+    else if (nzt <= NRM)
+        hipLaunchKernelGGL((k_zsum_gather<R, TKC, TH, CI, CO, NC, NRM>), grid, dim3(TKC * TH), 0, st, B, hx, Ly,
+                           Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
+    else if (nzs == 1)
+        hipLaunchKernelGGL((k_zsum_scatter<R, TKC, TH, CI, CO, NC, 1>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
+                           zs0, nzs, zt0, nzt, kt, prod, bm);
+    else if (nzs <= NRM)
+        hipLaunchKernelGGL((k_zsum_scatter<R, TKC, TH, CI, CO, NC, NRM>), grid, dim3(TKC * TH), 0, st, B, hx, Ly,
+                           Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1521,7 +1556,7 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
 {
     hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mo, 1);
     hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mp, 1);
-    const long long n = (long long)hx * nz * (Ly / 2 + 1);
+    const long long n = (long long)hx * nz * Ly;
     int blocks = (int)((n + kThreads - 1) / kThreads);
     blocks = blocks > 8192 ? 8192 : blocks;
     hipLaunchKernelGGL(k_extract_kt<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Zb, nz, scale,
