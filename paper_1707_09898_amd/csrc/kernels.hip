@@ -30,6 +30,15 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// v with its sign bit flipped where the mask's top bit is set (exact
+// multiplication by -1 without a branch on the value)
+__device__ __forceinline__ float flip_sign(float v, unsigned m) { return __uint_as_float(__float_as_uint(v) ^ m); }
+__device__ __forceinline__ double flip_sign(double v, unsigned m)
+{
+    return __hiloint2double(__double2hiint(v) ^ (int)m, __double2loint(v));
+}
+constexpr unsigned kSignBit = 0x80000000u;
+
 template <typename R>
 __device__ __forceinline__ R ipow_dev(R x, int p)
 {
@@ -720,22 +729,22 @@ __global__ __launch_bounds__(TKC *(L / E)) __attribute__((amdgpu_waves_per_eu(TO
     // tensor spectrum at this thread's frequencies, fetched before the data
     const int hLy = Ly / 2;
     const int kyq = live ? (ky <= hLy ? ky : Ly - ky) : 0;
-    const R sy = ky > hLy ? (R)-1 : (R)1;
+    const unsigned ysg = ky > hLy ? kSignBit : 0u;
     R K[NC][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int kz = p + P * m;
         const int kzq = kz <= L / 2 ? kz : L - kz;
-        const R sz = kz > L / 2 ? (R)-1 : (R)1;
+        const unsigned zsg = kz > L / 2 ? kSignBit : 0u;
         const long long at = ((long long)kx * spec.hkz + kzq) * spec.ky_pitch + kyq;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const int c = NC == 6 ? q : prod.comp[q];
-            R v = (NC < 6 || (prod.need >> c & 1)) ? spec.k[c * spec.comp_stride + at] : (R)0;
-            if (c == 3) v *= sy;             // xy: odd in y
-            else if (c == 4) v *= sz;        // xz: odd in z
-            else if (c == 5) v *= sy * sz;   // yz: odd in y and z
-            K[q][m] = v;
+            // parity signs as bit masks, so no branch waits on the load:
+            // xy odd in y, xz odd in z, yz odd in y and z
+            const unsigned oy = (c == 3 || c == 5) ? ~0u : 0u, oz = (c == 4 || c == 5) ? ~0u : 0u;
+            const R v = (NC < 6 || (prod.need >> c & 1)) ? spec.k[c * spec.comp_stride + at] : (R)0;
+            K[q][m] = flip_sign(v, (oy & ysg) ^ (oz & zsg));
         }
     }
 
@@ -753,8 +762,9 @@ __global__ __launch_bounds__(TKC *(L / E)) __attribute__((amdgpu_waves_per_eu(TO
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const int n = p + P * m;
-                X[i][m] = (live && n >= zs0 && n < zs0 + nzs) ? colp[i * cstride + (long long)(n - zs0) * bm.row]
-                                                              : cplx<R>{0, 0};
+                const int rc = min(max(n - zs0, 0), nzs - 1);
+                const cplx<R> xv = colp[i * cstride + (long long)rc * bm.row];
+                X[i][m] = (live && n >= zs0 && n < zs0 + nzs) ? xv : cplx<R>{0, 0};
             }
             regfft::fft_line<R, L, E>(X[i], tw, my, p, false);
         }
@@ -814,18 +824,19 @@ __global__ __launch_bounds__(TKC *(L / E)) __attribute__((amdgpu_waves_per_eu(TO
 // Column (kx, ky), rows in B relative to the source / target box.  Kt_q at
 // offset d = zt - zs, with the parity signs of its component; imaginary
 // components (xz, yz) multiply by i.
+// `d` must be a valid offset (|d| < nzk).
 template <typename R, int NC>
 __device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int ky, int d, R *K)
 {
     const int dq = d < 0 ? -d : d;
-    const R sd = d < 0 ? (R)-1 : (R)1;
+    const unsigned dsg = d < 0 ? kSignBit : 0u;
     const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + ky;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
         const int c = NC == 6 ? q : prod.comp[q];
-        R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
-        if (c == 4 || c == 5) v *= sd;   // xz, yz: odd in z
-        K[q] = v;
+        const unsigned oz = (c == 4 || c == 5) ? ~0u : 0u;   // xz, yz: odd in z
+        const R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
+        K[q] = flip_sign(v, oz & dsg);
     }
 }
 
@@ -843,8 +854,9 @@ __device__ __forceinline__ void zsum_mac(const ProductDev &prod, const R *K, con
             for (int q = 0; q < NC; ++q) {
                 const int c = NC == 6 ? q : prod.comp[q];
                 const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q];
-                if (c == 4 || c == 5) cim += w;
-                else cre += w;
+                const bool im = c == 4 || c == 5;
+                cre += im ? (R)0 : w;
+                cim += im ? w : (R)0;
             }
             out[o] = cadd(out[o], cmul(cplx<R>{cre, cim}, x[i]));
         }
@@ -878,19 +890,18 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_gather(cplx<R> *B, int hx, int
             R K[U][NR][NC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                // clamped rows keep every load in bounds and branch-free
                 const int zr = zr0 + u * TH;
                 const bool ok = zr < nzs;
+                const int zrc = min(zr, nzs - 1);
 #pragma unroll
-                for (int i = 0; i < CI; ++i)
-                    x[u][i] = ok ? colp[i * cstride + (long long)zr * bm.row] : cplx<R>{0, 0};
-#pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    if (r < nzt && ok) kt_at<R, NC>(kt, prod, kx, kyl, zt0 + r - (zs0 + zr), K[u][r]);
-                    else {
-#pragma unroll
-                        for (int q = 0; q < NC; ++q) K[u][r][q] = (R)0;
-                    }
+                for (int i = 0; i < CI; ++i) {
+                    const cplx<R> xv = colp[i * cstride + (long long)zrc * bm.row];
+                    x[u][i] = ok ? xv : cplx<R>{0, 0};
                 }
+                // rows past nzs carry x = 0; rows r >= nzt are never added
+#pragma unroll
+                for (int r = 0; r < NR; ++r) kt_at<R, NC>(kt, prod, kx, kyl, zt0 + min(r, nzt - 1) - (zs0 + zrc), K[u][r]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -933,8 +944,10 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_scatter(cplx<R> *B, int hx, in
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int i = 0; i < CI; ++i)
-            x[r][i] = (live && r < nzs) ? colp[i * cstride + (long long)r * bm.row] : cplx<R>{0, 0};
+        for (int i = 0; i < CI; ++i) {
+            const cplx<R> xv = colp[i * cstride + (long long)min(r, nzs - 1) * bm.row];
+            x[r][i] = (live && r < nzs) ? xv : cplx<R>{0, 0};
+        }
     __syncthreads();
     if (!live) return;
     constexpr int U = CI * NC <= 2 ? 16 : 4;
@@ -943,16 +956,10 @@ __global__ __launch_bounds__(TKC *TH) void k_zsum_scatter(cplx<R> *B, int hx, in
         R K[U][NR][NC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int zt = zt0 + zr0 + u * TH;
-            const bool ok = zr0 + u * TH < nzt;
+            // clamped rows: every load in bounds; rows past nzt are never stored
+            const int zt = zt0 + min(zr0 + u * TH, nzt - 1);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                if (r < nzs && ok) kt_at<R, NC>(kt, prod, kx, kyl, zt - (zs0 + r), K[u][r]);
-                else {
-#pragma unroll
-                    for (int q = 0; q < NC; ++q) K[u][r][q] = (R)0;
-                }
-            }
+            for (int r = 0; r < NR; ++r) kt_at<R, NC>(kt, prod, kx, kyl, zt - (zs0 + min(r, nzs - 1)), K[u][r]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -996,17 +1003,18 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 }
 
 // -- pass 1: real-to-complex FFT along x, transposed store ------------------
-// Block: NLC complex lines = 2 NLC source rows of one z (and one component).
-template <typename R, int L, int E, int NLC>
-__global__ __launch_bounds__(NLC *(L / E)) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src, Box S,
-                                                       cplx<R> *out, int hx, const cplx<R> *table)
+// Block: NLC complex lines = 2 NLC source rows of one z (and one component);
+// each thread transforms LPT of them in turn.
+template <typename R, int L, int E, int NLC, int LPT>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
+                                                                Box S, cplx<R> *out, int hx, const cplx<R> *table)
 {
     constexpr int P = L / E;
     constexpr int TY = 2 * NLC;
     constexpr int PITCH = regfft::padded_len(L);
     constexpr int NT = regfft::twiddle_count(L, E);
     __shared__ cplx<R> lds[NLC * PITCH];
-    const int l = line_of_thread<P>();
+    const int l0 = line_of_thread<P>();
     const int p = threadIdx.x % P;
     const int c = blockIdx.z;
     const int zrel = blockIdx.y;
@@ -1015,58 +1023,94 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xf_reg(int mode, DesignDev<R> 
     const int nrow = min(TY, S.y1 - ybase);
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
-    cplx<R> v[E];
-    const int r0 = 2 * l;
-    // row-level facts once; per element only the x range remains
-    const int yA = ybase + r0, yB = yA + 1;
-    const bool okA = r0 < nrow, okB = r0 + 1 < nrow;
-    if (mode == SRC_ARRAY) {
-        const R *rowA = src.ptr + c * src.cs + (long long)(z - src.oz) * src.zs + (long long)(yA - src.oy) * src.ys - src.ox;
-        const R *rowB = rowA + src.ys;
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int x = p + P * m;
-            const bool in = x >= S.x0 && x < S.x1;
-            v[m] = cplx<R>{(in && okA) ? rowA[x] : (R)0, (in && okB) ? rowB[x] : (R)0};
-        }
-    } else {
-        const bool inA = okA && dsg.design.has(dsg.design.x0, yA, z);
-        const bool inB = okB && dsg.design.has(dsg.design.x0, yB, z);
-        const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
-        const long long offA = ((long long)z * dsg.ny + yA) * dsg.nx, offB = offA + dsg.nx;
-        const R *rhoA = dsg.rho + offA, *rhoB = dsg.rho + offB;
-        const int xl = max(S.x0, dsg.design.x0), xh = min(S.x1, dsg.design.x1);
+    for (int j = 0; j < LPT; ++j) {
+        const int l = l0 + j * (NLC / LPT);
+        cplx<R> v[E];
+        const int r0 = 2 * l;
+        // row-level facts once; per element only the x range remains
+        const int yA = ybase + r0, yB = yA + 1;
+        const bool okA = r0 < nrow, okB = r0 + 1 < nrow;
+        if (mode == SRC_ARRAY) {
+            const R *rowZ = src.ptr + c * src.cs + (long long)(z - src.oz) * src.zs - src.ox;
+            const R *rowA = rowZ + (long long)((okA ? yA : ybase) - src.oy) * src.ys;
+            const R *rowB = rowZ + (long long)((okB ? yB : ybase) - src.oy) * src.ys;
+            R ra[E], rb[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int x = p + P * m;
-            const bool in = x >= xl && x < xh;
-            R a = (in && inA) ? ipow_dev(rhoA[x], dsg.p) : (R)0;
-            R b = (in && inB) ? ipow_dev(rhoB[x], dsg.p) : (R)0;
-            if (dsg.mask) {
-                if (in && inA && !dsg.mask[offA + x]) a = 0;
-                if (in && inB && !dsg.mask[offB + x]) b = 0;
+            for (int m = 0; m < E; ++m) {
+                const int xc = min(max(p + P * m, S.x0), S.x1 - 1);
+                ra[m] = rowA[xc];
+                rb[m] = rowB[xc];
+            }
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int x = p + P * m;
+                const bool in = x >= S.x0 && x < S.x1;
+                v[m] = cplx<R>{(in && okA) ? ra[m] : (R)0, (in && okB) ? rb[m] : (R)0};
+            }
+        } else {
+            const bool inA = okA && dsg.design.has(dsg.design.x0, yA, z);
+            const bool inB = okB && dsg.design.has(dsg.design.x0, yB, z);
+            const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
+            const long long offA = ((long long)z * dsg.ny + (okA ? yA : ybase)) * dsg.nx;
+            const long long offB = ((long long)z * dsg.ny + (okB ? yB : ybase)) * dsg.nx;
+            const R *rhoA = dsg.rho + offA, *rhoB = dsg.rho + offB;
+            const int xl = max(S.x0, dsg.design.x0), xh = min(S.x1, dsg.design.x1);
+            // every load from an address clamped into the row, all issued
+            // before the arithmetic; out-of-range elements are selected away
+            R ra[E], rb[E], fa[E], fb[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int xc = min(p + P * m, dsg.nx - 1);
+                ra[m] = rhoA[xc];
+                rb[m] = rhoB[xc];
+                fa[m] = fb[m] = (R)1;
             }
             if (mode == SRC_RHO_VECTOR) {
-                if (in && inA) a *= dsg.m0f[c * ncell + offA + x];
-                if (in && inB) b *= dsg.m0f[c * ncell + offB + x];
-            }
-            v[m] = cplx<R>{a, b};
-        }
-    }
-    cplx<R> *my = lds + l * PITCH;
-    regfft::fft_line<R, L, E>(v, tw, my, p, false);
-    // natural-order spectrum of every line into LDS, then split the pairs
 #pragma unroll
-    for (int m = 0; m < E; ++m) my[regfft::swz(p + P * m)] = v[m];
+                for (int m = 0; m < E; ++m) {
+                    const int xc = min(p + P * m, dsg.nx - 1);
+                    fa[m] = dsg.m0f[c * ncell + offA + xc];
+                    fb[m] = dsg.m0f[c * ncell + offB + xc];
+                }
+            }
+            if (dsg.mask) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int xc = min(p + P * m, dsg.nx - 1);
+                    if (!dsg.mask[offA + xc]) fa[m] = 0;
+                    if (!dsg.mask[offB + xc]) fb[m] = 0;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int x = p + P * m;
+                const bool in = x >= xl && x < xh;
+                const R a = (in && inA) ? ipow_dev(ra[m], dsg.p) * fa[m] : (R)0;
+                const R b = (in && inB) ? ipow_dev(rb[m], dsg.p) * fb[m] : (R)0;
+                v[m] = cplx<R>{a, b};
+            }
+        }
+        cplx<R> *my = lds + l * PITCH;
+        regfft::fft_line<R, L, E>(v, tw, my, p, false);
+        // natural-order spectrum of the line into LDS (its own slot)
+#pragma unroll
+        for (int m = 0; m < E; ++m) my[regfft::swz(p + P * m)] = v[m];
+    }
     __syncthreads();
+    // split the pairs and store TY consecutive y per kx
     const int nys = S.ny(), nzs = S.nz();
     const long long kxs = (long long)nzs * nys;
     cplx<R> *o = out + (long long)c * hx * kxs + (long long)zrel * nys + (ybase - S.y0);
     const R half = (R)0.5;
-    for (int e = threadIdx.x; e < hx * TY; e += blockDim.x) {
+    constexpr int NTH = (NLC / LPT) * P;
+    constexpr int NIT = ((L / 2 + 1) * TY + NTH - 1) / NTH;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + it * NTH;
         const int k = e / TY;
         const int r = e % TY;
-        if (r >= nrow) continue;
+        if (k >= hx || r >= nrow) continue;
         const cplx<R> *line = lds + (r >> 1) * PITCH;
         const cplx<R> Zk = line[regfft::swz(k)];
         const cplx<R> Zm = line[regfft::swz((L - k) & (L - 1))];
@@ -1078,11 +1122,12 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xf_reg(int mode, DesignDev<R> 
 }
 
 // -- pass 5: complex-to-real inverse FFT along x + epilogue -----------------
-// Block: NLC complex lines = 2 NLC target rows of one z, all CO components.
-template <typename R, int L, int E, int NLC, int CO>
-__global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi, View4<R> out,
-                                                       DesignDev<R> dsg, R m0u0, R m0u1, R m0u2, R *grad,
-                                                       const cplx<R> *table)
+// Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
+// each thread transforms LPT lines in turn.
+template <typename R, int L, int E, int NLC, int LPT, int CO>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
+                                                                View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
+                                                                R m0u2, R *grad, const cplx<R> *table)
 {
     constexpr int P = L / E;
     constexpr int TY = 2 * NLC;
@@ -1091,7 +1136,7 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int h
     constexpr int NT = regfft::twiddle_count(L, E);
     constexpr int NLDS = TY * HX > NLC * PITCH ? TY * HX : NLC * PITCH;   // staging or exchange
     __shared__ cplx<R> lds[NLDS];
-    const int l = line_of_thread<P>();
+    const int l0 = line_of_thread<P>();
     const int p = threadIdx.x % P;
     const int zrel = blockIdx.y;
     const int z = T.z0 + zrel;
@@ -1100,73 +1145,99 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int h
     const int nyt = T.ny(), nzt = T.nz();
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
-    const int rA = 2 * l, rB = 2 * l + 1;
     const R m0u[3] = {m0u0, m0u1, m0u2};
     const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
-    R acc[2][E];
+    R acc[LPT][2][E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) acc[0][m] = acc[1][m] = 0;
+    for (int j = 0; j < LPT; ++j)
+#pragma unroll
+        for (int m = 0; m < E; ++m) acc[j][0][m] = acc[j][1][m] = 0;
 #pragma unroll
     for (int cc = 0; cc < CO; ++cc) {
-        // stage the half spectra of the TY rows as [r][k]
-        for (int e = threadIdx.x; e < HX * TY; e += blockDim.x) {
+        // stage the half spectra of the TY rows as [r][k]: all loads first
+        // (a batch of registers), then the LDS stores
+        constexpr int NTH = (NLC / LPT) * P;
+        constexpr int NIT = (HX * TY + NTH - 1) / NTH;
+        cplx<R> stg[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = threadIdx.x + it * NTH;
             const int r = e % TY;
             const int k = e / TY;
-            lds[r * HX + k] = r < nrow ? C[((long long)(cc * hx + k) * nzt + zrel) * nyt + (ybase - T.y0 + r)]
-                                       : cplx<R>{0, 0};
+            stg[it] = (e < HX * TY && r < nrow)
+                          ? C[((long long)(cc * hx + k) * nzt + zrel) * nyt + (ybase - T.y0 + r)]
+                          : cplx<R>{0, 0};
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = threadIdx.x + it * NTH;
+            if (e < HX * TY) lds[(e % TY) * HX + e / TY] = stg[it];
         }
         __syncthreads();
-        cplx<R> v[E];
+        cplx<R> v[LPT][E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int k = p + P * m;
-            cplx<R> a, b;
-            if (k <= L / 2) {
-                a = lds[rA * HX + k];
-                b = lds[rB * HX + k];
-                if (k == 0 || k == L / 2) {
-                    a.y = 0;
-                    b.y = 0;
+        for (int j = 0; j < LPT; ++j) {
+            const int rA = 2 * (l0 + j * (NLC / LPT)), rB = rA + 1;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int k = p + P * m;
+                cplx<R> a, b;
+                if (k <= L / 2) {
+                    a = lds[rA * HX + k];
+                    b = lds[rB * HX + k];
+                    if (k == 0 || k == L / 2) {
+                        a.y = 0;
+                        b.y = 0;
+                    }
+                } else {
+                    a = cconj(lds[rA * HX + (L - k)]);
+                    b = cconj(lds[rB * HX + (L - k)]);
+                }
+                v[j][m] = cplx<R>{a.x - b.y, a.y + b.x};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int l = l0 + j * (NLC / LPT);
+            regfft::fft_line<R, L, E>(v[j], tw, lds + l * PITCH, p, true);
+        }
+        __syncthreads();   // the next component restages into the same LDS
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int l = l0 + j * (NLC / LPT);
+            if (!grad_epi) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int x = p + P * m;
+                    if (x < T.x0 || x >= T.x1) continue;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int r = 2 * l + h;
+                        if (r >= nrow) continue;
+                        const int y = ybase + r;
+                        out.ptr[cc * out.cs + (long long)(z - out.oz) * out.zs + (long long)(y - out.oy) * out.ys +
+                                (x - out.ox)] = h ? v[j][m].y : v[j][m].x;
+                    }
+                }
+            } else if (dsg.m0f) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    // columns past nx accumulate a clamped value and are never stored
+                    const int xc = min(p + P * m, dsg.nx - 1);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int y = min(ybase + 2 * l + h, dsg.ny - 1);
+                        acc[j][h][m] += dsg.m0f[cc * ncell + ((long long)z * dsg.ny + y) * dsg.nx + xc] *
+                                        (h ? v[j][m].y : v[j][m].x);
+                    }
                 }
             } else {
-                a = cconj(lds[rA * HX + (L - k)]);
-                b = cconj(lds[rB * HX + (L - k)]);
-            }
-            v[m] = cplx<R>{a.x - b.y, a.y + b.x};
-        }
-        __syncthreads();
-        regfft::fft_line<R, L, E>(v, tw, lds + l * PITCH, p, true);
-        __syncthreads();   // the next component restages into the same LDS
-        if (!grad_epi) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int x = p + P * m;
-                if (x < T.x0 || x >= T.x1) continue;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = 2 * l + h;
-                    if (r >= nrow) continue;
-                    const int y = ybase + r;
-                    out.ptr[cc * out.cs + (long long)(z - out.oz) * out.zs + (long long)(y - out.oy) * out.ys +
-                            (x - out.ox)] = h ? v[m].y : v[m].x;
+                for (int m = 0; m < E; ++m) {
+                    acc[j][0][m] += m0u[cc] * v[j][m].x;
+                    acc[j][1][m] += m0u[cc] * v[j][m].y;
                 }
-            }
-        } else if (dsg.m0f) {
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int x = p + P * m;
-                if (x >= dsg.nx) continue;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int y = min(ybase + 2 * l + h, dsg.ny - 1);
-                    acc[h][m] += dsg.m0f[cc * ncell + ((long long)z * dsg.ny + y) * dsg.nx + x] * (h ? v[m].y : v[m].x);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                acc[0][m] += m0u[cc] * v[m].x;
-                acc[1][m] += m0u[cc] * v[m].y;
             }
         }
     }
@@ -1174,22 +1245,37 @@ __global__ __launch_bounds__(NLC *(L / E)) void k_xi_reg(const cplx<R> *C, int h
         // whole x rows: p rho^(p-1) acc inside the design region, zero elsewhere
         const int xl = max(T.x0, dsg.design.x0), xh = min(T.x1, dsg.design.x1);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 2 * l + h;
-            if (r >= nrow) continue;
-            const int y = ybase + r;
-            const bool rowin = dsg.design.has(dsg.design.x0, y, z);
-            const long long off = ((long long)z * dsg.ny + y) * dsg.nx;
-            const R *rho = dsg.rho + off;
-            R *gr = grad + off;
+        for (int j = 0; j < LPT; ++j) {
+            const int l = l0 + j * (NLC / LPT);
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int x = p + P * m;
-                if (x >= dsg.nx) continue;
-                R g = 0;
-                if (rowin && x >= xl && x < xh && (!dsg.mask || dsg.mask[off + x]))
-                    g = (R)dsg.p * ipow_dev(rho[x], dsg.p - 1) * acc[h][m];
-                gr[x] = g;
+            for (int h = 0; h < 2; ++h) {
+                const int r = 2 * l + h;
+                if (r >= nrow) continue;
+                const int y = ybase + r;
+                const bool rowin = dsg.design.has(dsg.design.x0, y, z);
+                const long long off = ((long long)z * dsg.ny + y) * dsg.nx;
+                const R *rho = dsg.rho + off;
+                R *gr = grad + off;
+                R rv[E];
+                bool mk[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    rv[m] = rho[min(p + P * m, dsg.nx - 1)];
+                    mk[m] = true;
+                }
+                if (dsg.mask) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) mk[m] = dsg.mask[off + min(p + P * m, dsg.nx - 1)] != 0;
+                }
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int x = p + P * m;
+                    if (x >= dsg.nx) continue;
+                    R g = 0;
+                    if (rowin && x >= xl && x < xh && mk[m])
+                        g = (R)dsg.p * ipow_dev(rv[m], dsg.p - 1) * acc[j][h][m];
+                    gr[x] = g;
+                }
             }
         }
     }
@@ -1215,11 +1301,17 @@ hipError_t allow_lds(K kernel, size_t bytes)
 #ifndef TOF_X_NLC512
 #define TOF_X_NLC512 8
 #endif
+#ifndef TOF_X_LPT512
+#define TOF_X_LPT512 1
+#endif
 #ifndef TOF_X_NLC256
 #define TOF_X_NLC256 8
 #endif
+#ifndef TOF_X_LPT256
+#define TOF_X_LPT256 1
+#endif
 
-template <typename R, int L, int NLC>
+template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
                          const FftPlanDev &plan, cplx<R> *out, int hx)
 {
@@ -1227,13 +1319,13 @@ hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View
     if ((long long)((S.ny() + 2 * NLC - 1) / (2 * NLC)) * S.nz() * c_in < 512) {
         // few rows: one row pair per block
         dim3 grid((S.ny() + 1) / 2, S.nz(), c_in);
-        hipLaunchKernelGGL((k_xf_reg<R, L, E, 1>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
+        hipLaunchKernelGGL((k_xf_reg<R, L, E, 1, 1>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
                            (const cplx<R> *)plan.tw);
         return hipGetLastError();
     }
     dim3 grid((S.ny() + 2 * NLC - 1) / (2 * NLC), S.nz(), c_in);
-    hipLaunchKernelGGL((k_xf_reg<R, L, E, NLC>), grid, dim3(NLC * (L / E)), 0, st, mode, dsg, src, S, out, hx,
-                       (const cplx<R> *)plan.tw);
+    hipLaunchKernelGGL((k_xf_reg<R, L, E, NLC, LPT>), grid, dim3((NLC / LPT) * (L / E)), 0, st, mode, dsg, src, S,
+                       out, hx, (const cplx<R> *)plan.tw);
     return hipGetLastError();
 }
 
@@ -1242,11 +1334,11 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
                             Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx)
 {
     switch (plan.L) {
-    case 32: return launch_xf_reg<R, 32, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 64: return launch_xf_reg<R, 64, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 128: return launch_xf_reg<R, 128, 16>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 256: return launch_xf_reg<R, 256, TOF_X_NLC256>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 512: return launch_xf_reg<R, 512, TOF_X_NLC512>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 32: return launch_xf_reg<R, 32, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 64: return launch_xf_reg<R, 64, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 128: return launch_xf_reg<R, 128, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 256: return launch_xf_reg<R, 256, TOF_X_NLC256, TOF_X_LPT256>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 512: return launch_xf_reg<R, 512, TOF_X_NLC512, TOF_X_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx);
     default: break;
     }
     const int L = plan.L;
@@ -1386,20 +1478,21 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
     return hipGetLastError();
 }
 
-template <typename R, int L, int NLC>
+template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T, const FftPlanDev &plan,
                          bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad)
 {
     constexpr int E = 8;
     if ((long long)((T.ny() + 2 * NLC - 1) / (2 * NLC)) * T.nz() < 512 && NLC > 1)
-        return launch_xi_reg<R, L, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        return launch_xi_reg<R, L, 1, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
     dim3 grid((T.ny() + 2 * NLC - 1) / (2 * NLC), T.nz());
+    dim3 block((NLC / LPT) * (L / E));
     if (c == 1)
-        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, 1>), grid, dim3(NLC * (L / E)), 0, st, C, hx, T,
-                           grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
+        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, LPT, 1>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
+                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
     else if (c == 3)
-        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, 3>), grid, dim3(NLC * (L / E)), 0, st, C, hx, T,
-                           grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
+        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, LPT, 3>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
+                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1412,11 +1505,15 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
 {
     if (c == 1 || c == 3) {
         switch (plan.L) {
-        case 32: return launch_xi_reg<R, 32, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 64: return launch_xi_reg<R, 64, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 128: return launch_xi_reg<R, 128, 16>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 256: return launch_xi_reg<R, 256, TOF_X_NLC256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 512: return launch_xi_reg<R, 512, TOF_X_NLC512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 128: return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 256:
+            return launch_xi_reg<R, 256, TOF_X_NLC256, TOF_X_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
+                                                                    grad);
+        case 512:
+            return launch_xi_reg<R, 512, TOF_X_NLC512, TOF_X_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
+                                                                    grad);
         default: break;
         }
     }
