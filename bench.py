@@ -120,8 +120,9 @@ def main():
         for _ in range(args.profile_steps):
             e.objective_and_grad(rho, grad, J)
         prof = e.profile_read()
+        kernels = e.profile_kernels()
         e.profile(False)
-        results[dtype] = {"ms": ms, "prof": prof, "L": L, "J": float(J.item())}
+        results[dtype] = {"ms": ms, "prof": prof, "kernels": kernels, "L": L, "J": float(J.item())}
         print(f"[bench] {dtype}: {ms:.4f} ms/eval, {1000.0 / ms:.1f} evals/s, J={J.item():.10e}",
               file=sys.stderr, flush=True)
         e.close()
@@ -157,8 +158,9 @@ def main():
         "speedup_f32_over_f64": results["f64"]["ms"] / r32["ms"],
         "bytes_per_eval": {"passes": pass_bytes, "full_field_model": model},
         "effective_GBps": {"passes": pass_bytes * evals / 1e9, "full_field_model": model * evals / 1e9},
-        "per_kernel_us": {name: round(avg * 1e3, 2) for (name, avg, _, _) in slots},
-        "roofline": {"bound": "hbm", "kernel": f"{tof.PROFILE_KERNELS[dom_idx]} ({dom[0]})",
+        "per_kernel_us": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)]}": round(avg * 1e3, 2)
+                          for (name, avg, _, _) in slots},
+        "roofline": {"bound": "hbm", "kernel": f"{r32['kernels'][dom_idx]} ({dom[0]})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": dom[3], "avg_launch_us": dom[1] * 1e3},

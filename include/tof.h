@@ -181,7 +181,9 @@ tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream);
  * 0-4 the passes of the forward convolution (x, y, z with the tensor product,
  * inverse y, inverse x with its epilogue), 5 the objective, 6-10 the passes of
  * the adjoint convolution, 11 the zero fill of the gradient outside the design
- * region.  At most 1024 calls are recorded between reads; later ones are not
+ * region.  With the fused y / z-sum kernels (TOF_OPT_FUSE_YZ) slot 2 (8 in
+ * the adjoint) holds the fused kernel, slot 1 (7) is unused, and slot 3 (9)
+ * holds the inverse y pass after a gather and is unused after a scatter.  At most 1024 calls are recorded between reads; later ones are not
  * timed.  Errors: TOF_ERR_INVALID, TOF_ERR_HIP.
  */
 #define TOF_PROFILE_SLOTS 12
@@ -196,6 +198,27 @@ tof_status tof_profile_enable(tof_ctx *ctx, int32_t enable);
  * TOF_ERR_HIP.
  */
 tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[], double bytes_host[]);
+
+/*
+ * Name of the kernel last timed in a slot (e.g. "k_yzsum_gather"), "" if
+ * none; valid until the next timed call on the context.
+ */
+const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot);
+
+/*
+ * Pass choices, each 0 or 1 (default 1); the result is the same convolution
+ * either way, up to rounding order.
+ *   TOF_OPT_ZSUM     when the source or the target spans at most 4 z rows,
+ *                    the z pass is a direct sum against the tensor
+ *                    transformed along x and y, instead of FFTs along z.
+ *   TOF_OPT_FUSE_YZ  that direct sum runs fused with the y transforms
+ *                    (power-of-two Ly from 32 to 512), so the y spectra of
+ *                    the many-row side never go through device memory.
+ * Errors: TOF_ERR_INVALID.
+ */
+#define TOF_OPT_ZSUM 1
+#define TOF_OPT_FUSE_YZ 2
+tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value);
 
 /* Padded lengths chosen for the context: out[0..2] = Lx, Ly, Lz. */
 tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3]);

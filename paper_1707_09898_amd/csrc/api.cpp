@@ -14,6 +14,8 @@
 #include "dd.h"
 #include "engine.h"
 
+thread_local const char *g_last_kernel = "";
+
 namespace {
 
 thread_local std::string g_thread_error;
@@ -79,12 +81,17 @@ struct tof_ctx {
     int prof_calls[TOF_PROFILE_SLOTS] = {};
     std::vector<hipEvent_t> prof_ev;   // [slot][call][2]
     double prof_bytes[TOF_PROFILE_SLOTS] = {};
+    std::string prof_kernel[TOF_PROFILE_SLOTS];
+    // pass choices (tof_set_option)
+    bool opt_zsum = true;    // direct z sum against Kt for few source / target rows
+    bool opt_fuse = true;    // that sum fused with the y transforms
     std::string err;
 };
 
 namespace {
 
 constexpr int kProfCalls = 1024;
+constexpr int kYzBlocks = 2048;   // blocks a fused y / z-sum launch aims for (several per CU)
 
 tof_status fail(tof_ctx *ctx, tof_status st, const std::string &msg)
 {
@@ -120,6 +127,10 @@ hipError_t timed(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn)
     if (e != hipSuccess) return e;
     ctx->prof_calls[slot]++;
     ctx->prof_bytes[slot] = bytes;
+    // the launch expression, e.g. "(k_xi_reg<R, L, ...>)", reduced to the kernel's name
+    std::string k = g_last_kernel;
+    if (!k.empty() && k[0] == '(') k = k.substr(1);
+    ctx->prof_kernel[slot] = k.substr(0, k.find_first_of("<(), "));
     return hipSuccess;
 }
 
@@ -264,18 +275,53 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
     HIP_TRY(ctx, timed(ctx, st, slot0 + 0, src_bytes + a_elems * cw, [&] {
         return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx);
     }));
+    const bool zsum_counts = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
+    const bool few = ctx->opt_zsum && zsum_counts && (S.nz() <= kZsumMaxRows || T.nz() <= kZsumMaxRows);
+    KtDev<R> kt{(const R *)ctx->kt.p, ctx->comp_stride_kt, ctx->nz, ctx->kt_pitch};
+    const int drows = std::min(ctx->nz, S.nz() + T.nz() - 1);
+    const double kt_bytes = ncomp * (double)hx * drows * Ly * w;
+    if (few && ctx->opt_fuse) {
+        // y transforms fused with the direct z sum: no y spectra in HBM
+        YzSumArgs<R> ya{A, B, C, hx, S.y0, S.ny(), S.z0, S.nz(), T.y0, T.ny(), T.z0, T.nz(), 1};
+        const bool gather = T.nz() <= kZsumMaxRows;
+        const int rows = gather ? S.nz() : T.nz();
+        // enough blocks to fill the chip; the gather's partial rows must fit in B
+        int G = std::max(1, std::min(rows, (kYzBlocks + hx - 1) / hx));
+        const long long part_rows = (long long)prod.c_out * hx * T.nz() * Ly;
+        if (gather) G = (int)std::max(1LL, std::min<long long>(G, (long long)(ctx->B.bytes / sizeof(cplx<R>)) / part_rows));
+        ya.rpg = (rows + G - 1) / G;
+        G = (rows + ya.rpg - 1) / ya.rpg;
+        if (launch_yz_sum<R>(st, ya, kt, prod, ply, true) == hipSuccess) {
+            const double part_bytes = (double)G * part_rows * cw;
+            if (gather) {
+                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_bytes + part_bytes, [&] {
+                    return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
+                }));
+                const BlockMap flat{30, 0, 0};
+                HIP_TRY(ctx, timed(ctx, st, slot0 + 3, part_bytes + c_elems * cw, [&] {
+                    return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)T.nz() * Ly, Ly,
+                                              (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true, flat,
+                                              flat, G, part_rows);
+                }));
+            } else {
+                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_bytes + c_elems * cw, [&] {
+                    return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
+                }));
+            }
+            HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
+                return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad);
+            }));
+            return TOF_OK;
+        }
+    }
     const BlockMap plain{30, 0, 0};
     const BlockMap bm = ctx->bmap;
     HIP_TRY(ctx, timed(ctx, st, slot0 + 1, (a_elems + b_in) * cw, [&] {
         return launch_line_fft<R>(st, A, B, prod.c_in * hx * S.nz(), S.nz(), (long long)S.nz() * S.ny(), S.ny(),
                                   (long long)Zr * Ly, bm.row, S.y0, S.ny(), 0, Ly, ply, false, plain, bm);
     }));
-    const bool zsum_counts = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
-    if (zsum_counts && (S.nz() <= kZsumMaxRows || T.nz() <= kZsumMaxRows)) {
+    if (few) {
         // few source or target rows: direct sum against the x-y transformed tensor
-        KtDev<R> kt{(const R *)ctx->kt.p, ctx->comp_stride_kt, ctx->nz, ctx->kt_pitch};
-        const int drows = std::min(ctx->nz, S.nz() + T.nz() - 1);
-        const double kt_bytes = ncomp * (double)hx * drows * Ly * w;
         HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + kt_bytes, [&] {
             return launch_z_sum<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), kt, prod, bm);
         }));
@@ -775,6 +821,23 @@ tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[]
         ctx->prof_calls[slot] = 0;
     }
     return TOF_OK;
+}
+
+const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot)
+{
+    if (!ctx || slot < 0 || slot >= TOF_PROFILE_SLOTS) return "";
+    return ctx->prof_kernel[slot].c_str();
+}
+
+tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (value != 0 && value != 1) return fail(ctx, TOF_ERR_INVALID, "option values are 0 or 1");
+    switch (option) {
+    case TOF_OPT_ZSUM: ctx->opt_zsum = value != 0; return TOF_OK;
+    case TOF_OPT_FUSE_YZ: ctx->opt_fuse = value != 0; return TOF_OK;
+    default: return fail(ctx, TOF_ERR_INVALID, "unknown option");
+    }
 }
 
 tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3])

@@ -1,0 +1,71 @@
+// Device helpers shared by the pass kernels (kernels.hip) and the fused
+// y-transform / z-sum kernels (yzsum.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+#include "fft.h"
+
+namespace tofdev {
+
+// v with its sign bit flipped where the mask's top bit is set (exact
+// multiplication by -1 without a branch on the value)
+__device__ __forceinline__ float flip_sign(float v, unsigned m) { return __uint_as_float(__float_as_uint(v) ^ m); }
+__device__ __forceinline__ double flip_sign(double v, unsigned m)
+{
+    return __hiloint2double(__double2hiint(v) ^ (int)m, __double2loint(v));
+}
+constexpr unsigned kSignBit = 0x80000000u;
+
+// Line index of the calling thread when P threads share a line.  With P a
+// multiple of the wave size every wave lies inside one line, so the index is
+// made wave-uniform (scalar registers: row pointers need no per-lane math).
+template <int P>
+__device__ __forceinline__ int line_of_thread()
+{
+    const int l = threadIdx.x / P;
+    if constexpr (P % 64 == 0) return __builtin_amdgcn_readfirstlane(l);
+    return l;
+}
+
+// Kt_q(kx, ky, d) for the product's NC components, with the parity sign of
+// the z offset (xz and yz are odd in z); `d` must satisfy |d| < nzk.
+template <typename R, int NC>
+__device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int ky, int d, R *K)
+{
+    const int dq = d < 0 ? -d : d;
+    const unsigned dsg = d < 0 ? kSignBit : 0u;
+    const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + ky;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        const int c = NC == 6 ? q : prod.comp[q];
+        const unsigned oz = (c == 4 || c == 5) ? ~0u : 0u;   // xz, yz: odd in z
+        const R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
+        K[q] = flip_sign(v, oz & dsg);
+    }
+}
+
+// out_o += sum_i (sum_q W[o][i][q] K_q) x_i; K_q is real, or imaginary
+// (the stored value times i) for the components odd in x (xz, yz).
+template <typename R, int CI, int CO, int NC>
+__device__ __forceinline__ void zsum_mac(const ProductDev &prod, const R *K, const cplx<R> *x, cplx<R> *out)
+{
+#pragma unroll
+    for (int o = 0; o < CO; ++o)
+#pragma unroll
+        for (int i = 0; i < CI; ++i) {
+            R cre = 0, cim = 0;
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                const int c = NC == 6 ? q : prod.comp[q];
+                const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q];
+                const bool im = c == 4 || c == 5;
+                cre += im ? (R)0 : w;
+                cim += im ? w : (R)0;
+            }
+            out[o] = cadd(out[o], cmul(cplx<R>{cre, cim}, x[i]));
+        }
+}
+
+}  // namespace tofdev

@@ -99,17 +99,41 @@ struct KtDev {
 // rows below which the z pass sums against Kt instead of transforming
 constexpr int kZsumMaxRows = 4;
 
+// Arguments of the fused y-transform / z-sum kernels (yzsum.hip).
+template <typename R>
+struct YzSumArgs {
+    const cplx<R> *A;        // x-pass output [c_in][hx][nzs][nys]
+    cplx<R> *part;           // gather: partial spectra [G][c_out][hx][nzt][Ly]
+    cplx<R> *C;              // scatter: inverse-x input [c_out][hx][nzt][nyt]
+    int hx;
+    int ys0, nys, zs0, nzs;  // source box rows
+    int yt0, nyt, zt0, nzt;  // target box rows
+    int rpg;                 // rows per block group: source rows (gather) or target rows (scatter)
+};
+
+// Text of the kernel expression last launched by this thread (for the
+// per-launch timing record); set by TOF_LAUNCH.
+extern thread_local const char *g_last_kernel;
+#define TOF_LAUNCH(K, ...)                 \
+    do {                                   \
+        g_last_kernel = #K;                \
+        hipLaunchKernelGGL(K, __VA_ARGS__); \
+    } while (0)
+
 // ---- host launchers (kernels.hip); all enqueue on `st` and return hipError_t ----
 
 template <typename R>
 hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
                             Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx);
 
+// nsum > 1 (power-of-two lengths only): the input line is the sum, in order,
+// of nsum lines sum_stride elements apart.
 template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
                            long long out_inner, int p_in, int n_in, int p_out, int n_out,
-                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout);
+                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout, int nsum = 1,
+                           long long sum_stride = 0);
 
 template <typename R>
 hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,
@@ -120,6 +144,14 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
 template <typename R>
 hipError_t launch_z_sum(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs, int zt0, int nzt,
                         const KtDev<R> &kt, const ProductDev &prod, BlockMap bm);
+
+// Passes 2-4 fused (yzsum.hip): the gather (nzt <= kZsumMaxRows) writes
+// partial spectra for an inverse y pass with nsum = ceil(nzs / rpg); the
+// scatter (nzs <= kZsumMaxRows) writes C.  Requires a power-of-two Ly in
+// [32, 512].  check_only: report whether the case is supported, launch nothing.
+template <typename R>
+hipError_t launch_yz_sum(hipStream_t st, const YzSumArgs<R> &a, const KtDev<R> &kt, const ProductDev &prod,
+                         const FftPlanDev &plan, bool check_only);
 
 template <typename R>
 hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Zb, int nz, double scale,

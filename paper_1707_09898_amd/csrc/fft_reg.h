@@ -16,7 +16,12 @@
 
 namespace regfft {
 
-constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+constexpr int ilog2c(int v)
+{
+    int n = 0;
+    while (v > 1) v /= 2, ++n;
+    return n;
+}
 
 // LDS slot of line position i: one pad slot per 32 complex keeps the
 // exchange's strided accesses from piling onto one bank.  A line occupies
@@ -29,7 +34,12 @@ constexpr int full_stages(int L, int E) { return ilog2c(L) / ilog2c(E); }
 constexpr int last_radix(int L, int E) { return L >> (full_stages(L, E) * ilog2c(E)); }
 constexpr int num_stages(int L, int E) { return full_stages(L, E) + (last_radix(L, E) > 1 ? 1 : 0); }
 constexpr int stage_radix(int L, int E, int s) { return s < full_stages(L, E) ? E : last_radix(L, E); }
-constexpr int stage_ns(int L, int E, int s) { return s == 0 ? 1 : stage_ns(L, E, s - 1) * stage_radix(L, E, s - 1); }
+constexpr int stage_ns(int L, int E, int s)
+{
+    int n = 1;   // a loop, not recursion: always inlined where it is not folded
+    for (int q = 0; q < s; ++q) n *= stage_radix(L, E, q);
+    return n;
+}
 // twiddle slots (complex) a thread keeps: stages 1.. need (E/R)(R-1) each
 constexpr int twiddle_count(int L, int E)
 {

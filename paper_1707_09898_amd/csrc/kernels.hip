@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dd.h"
+#include "device_common.h"
 #include "engine.h"
 #include "fft_reg.h"
 
@@ -28,16 +29,10 @@
 
 namespace {
 
+using namespace tofdev;
+
 constexpr int kThreads = 256;
 
-// v with its sign bit flipped where the mask's top bit is set (exact
-// multiplication by -1 without a branch on the value)
-__device__ __forceinline__ float flip_sign(float v, unsigned m) { return __uint_as_float(__float_as_uint(v) ^ m); }
-__device__ __forceinline__ double flip_sign(double v, unsigned m)
-{
-    return __hiloint2double(__double2hiint(v) ^ (int)m, __double2loint(v));
-}
-constexpr unsigned kSignBit = 0x80000000u;
 
 template <typename R>
 __device__ __forceinline__ R ipow_dev(R x, int p)
@@ -641,16 +636,6 @@ __global__ __launch_bounds__(kThreads) void k_extract_spectrum(const cplx<double
     atomicMax(mx_real, (unsigned long long)__double_as_longlong(mr));
 }
 
-// Line index of the calling thread when P threads share a line.  With P a
-// multiple of the wave size every wave lies inside one line, so the index is
-// made wave-uniform (scalar registers: row pointers need no per-lane math).
-template <int P>
-__device__ __forceinline__ int line_of_thread()
-{
-    const int l = threadIdx.x / P;
-    if constexpr (P % 64 == 0) return __builtin_amdgcn_readfirstlane(l);
-    return l;
-}
 
 // ===========================================================================
 // Register-resident variants for power-of-two lengths fixed at compile time.
@@ -663,7 +648,7 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
                                                         long long in_outer, long long in_inner, long long out_outer,
                                                         long long out_inner, int p_in, int n_in, int p_out,
                                                         int n_out, const cplx<R> *table, int inv, BlockMap bin,
-                                                        BlockMap bout)
+                                                        BlockMap bout, int nsum, long long sum_stride)
 {
     constexpr int P = L / E;
     constexpr int PITCH = regfft::padded_len(L);
@@ -676,11 +661,25 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
     cplx<R> v[E];
-    const long long ib = (long long)(line / inner) * in_outer + (long long)(line % inner) * in_inner;
+    const int lc = live ? line : 0;   // a dead slot reads line 0 and stores nothing
+    const long long ib = (long long)(lc / inner) * in_outer + (long long)(lc % inner) * in_inner;
+    long long at[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) at[m] = ib + bin.at(min(max(p + P * m - p_in, 0), n_in - 1));
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = in[at[m]];
+    // partial lines added in order
+    for (int g = 1; g < nsum; ++g) {
+        cplx<R> w[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) w[m] = in[at[m] + g * sum_stride];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = cadd(v[m], w[m]);
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int n = p + P * m;
-        v[m] = (live && n >= p_in && n < p_in + n_in) ? in[ib + bin.at(n - p_in)] : cplx<R>{0, 0};
+        if (!(live && n >= p_in && n < p_in + n_in)) v[m] = cplx<R>{0, 0};
     }
     regfft::fft_line<R, L, E>(v, tw, lds + l * PITCH, p, inv != 0);
     if (live) {
@@ -824,43 +823,7 @@ __global__ __launch_bounds__(TKC *(L / E)) __attribute__((amdgpu_waves_per_eu(TO
 // Column (kx, ky), rows in B relative to the source / target box.  Kt_q at
 // offset d = zt - zs, with the parity signs of its component; imaginary
 // components (xz, yz) multiply by i.
-// `d` must be a valid offset (|d| < nzk).
-template <typename R, int NC>
-__device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int ky, int d, R *K)
-{
-    const int dq = d < 0 ? -d : d;
-    const unsigned dsg = d < 0 ? kSignBit : 0u;
-    const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + ky;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-        const int c = NC == 6 ? q : prod.comp[q];
-        const unsigned oz = (c == 4 || c == 5) ? ~0u : 0u;   // xz, yz: odd in z
-        const R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
-        K[q] = flip_sign(v, oz & dsg);
-    }
-}
 
-// out_o += sum_i (sum_q W[o][i][q] K_q) x_i; K_q is real, or imaginary
-// (the stored value times i) for the components odd in x (xz, yz).
-template <typename R, int CI, int CO, int NC>
-__device__ __forceinline__ void zsum_mac(const ProductDev &prod, const R *K, const cplx<R> *x, cplx<R> *out)
-{
-#pragma unroll
-    for (int o = 0; o < CO; ++o)
-#pragma unroll
-        for (int i = 0; i < CI; ++i) {
-            R cre = 0, cim = 0;
-#pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                const int c = NC == 6 ? q : prod.comp[q];
-                const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q];
-                const bool im = c == 4 || c == 5;
-                cre += im ? (R)0 : w;
-                cim += im ? w : (R)0;
-            }
-            out[o] = cadd(out[o], cmul(cplx<R>{cre, cim}, x[i]));
-        }
-}
 
 // Few target rows: TH threads per column split the source rows; partial
 // sums are added in thread order through LDS.
@@ -1319,12 +1282,12 @@ hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View
     if ((long long)((S.ny() + 2 * NLC - 1) / (2 * NLC)) * S.nz() * c_in < 512) {
         // few rows: one row pair per block
         dim3 grid((S.ny() + 1) / 2, S.nz(), c_in);
-        hipLaunchKernelGGL((k_xf_reg<R, L, E, 1, 1>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
+        TOF_LAUNCH((k_xf_reg<R, L, E, 1, 1>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
                            (const cplx<R> *)plan.tw);
         return hipGetLastError();
     }
     dim3 grid((S.ny() + 2 * NLC - 1) / (2 * NLC), S.nz(), c_in);
-    hipLaunchKernelGGL((k_xf_reg<R, L, E, NLC, LPT>), grid, dim3((NLC / LPT) * (L / E)), 0, st, mode, dsg, src, S,
+    TOF_LAUNCH((k_xf_reg<R, L, E, NLC, LPT>), grid, dim3((NLC / LPT) * (L / E)), 0, st, mode, dsg, src, S,
                        out, hx, (const cplx<R> *)plan.tw);
     return hipGetLastError();
 }
@@ -1350,7 +1313,7 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
     hipError_t e = allow_lds(k_x_forward<R>, lds);
     if (e != hipSuccess) return e;
     dim3 grid((S.ny() + TY - 1) / TY, S.nz(), c_in);
-    hipLaunchKernelGGL(k_x_forward<R>, grid, dim3(kThreads), lds, st, mode, dsg, src, S, plan, out, hx,
+    TOF_LAUNCH(k_x_forward<R>, grid, dim3(kThreads), lds, st, mode, dsg, src, S, plan, out, hx,
                        TY, pitch);
     return hipGetLastError();
 }
@@ -1359,21 +1322,21 @@ template <typename R, int L>
 hipError_t launch_line_reg(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer, long long out_inner,
                            int p_in, int n_in, int p_out, int n_out, const FftPlanDev &plan, bool inv, BlockMap bin,
-                           BlockMap bout)
+                           BlockMap bout, int nsum, long long sum_stride)
 {
     constexpr int E = 8;
     constexpr int NL = 256 / (L / E);
     if (nlines < 2048) {
         // few lines (the sensor plane): one line per block spreads them over more CUs
-        hipLaunchKernelGGL((k_line_reg<R, L, E, 1>), dim3(nlines), dim3(L / E), 0, st, in, out, nlines, inner,
+        TOF_LAUNCH((k_line_reg<R, L, E, 1>), dim3(nlines), dim3(L / E), 0, st, in, out, nlines, inner,
                            in_outer, in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out,
-                           (const cplx<R> *)plan.tw, inv ? 1 : 0, bin, bout);
+                           (const cplx<R> *)plan.tw, inv ? 1 : 0, bin, bout, nsum, sum_stride);
         return hipGetLastError();
     }
     dim3 grid((nlines + NL - 1) / NL);
-    hipLaunchKernelGGL((k_line_reg<R, L, E, NL>), grid, dim3(256), 0, st, in, out, nlines, inner, in_outer,
+    TOF_LAUNCH((k_line_reg<R, L, E, NL>), grid, dim3(256), 0, st, in, out, nlines, inner, in_outer,
                        in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, (const cplx<R> *)plan.tw,
-                       inv ? 1 : 0, bin, bout);
+                       inv ? 1 : 0, bin, bout, nsum, sum_stride);
     return hipGetLastError();
 }
 
@@ -1381,13 +1344,15 @@ template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
                            long long out_inner, int p_in, int n_in, int p_out, int n_out,
-                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout)
+                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout, int nsum,
+                           long long sum_stride)
 {
     if (nlines <= 0) return hipSuccess;
+    if (nsum < 1) return hipErrorInvalidValue;
 #define TOF_LINE_CASE(LL)                                                                                    \
     case LL:                                                                                                 \
         return launch_line_reg<R, LL>(st, in, out, nlines, inner, in_outer, in_inner, out_outer, out_inner, \
-                                      p_in, n_in, p_out, n_out, plan, inv, bin, bout);
+                                      p_in, n_in, p_out, n_out, plan, inv, bin, bout, nsum, sum_stride);
     switch (plan.L) {
         TOF_LINE_CASE(32)
         TOF_LINE_CASE(64)
@@ -1397,6 +1362,7 @@ hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
     default: break;
     }
 #undef TOF_LINE_CASE
+    if (nsum != 1) return hipErrorInvalidValue;   // partial sums: register lengths only
     const int pitch = plan.L + 1;
     const size_t per_line = 2 * (size_t)pitch * sizeof(cplx<R>);
     int NL = (int)(kLdsBudget / per_line);
@@ -1405,7 +1371,7 @@ hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
     hipError_t e = allow_lds(k_line_fft<R>, lds);
     if (e != hipSuccess) return e;
     dim3 grid((nlines + NL - 1) / NL);
-    hipLaunchKernelGGL(k_line_fft<R>, grid, dim3(kThreads), lds, st, in, out, nlines, inner, in_outer,
+    TOF_LAUNCH(k_line_fft<R>, grid, dim3(kThreads), lds, st, in, out, nlines, inner, in_outer,
                        in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, plan, inv ? 1 : 0, NL,
                        pitch, bin, bout);
     return hipGetLastError();
@@ -1427,7 +1393,7 @@ hipError_t launch_z_reg(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, i
     constexpr int TKC = TKC0 * P > 1024 ? 1024 / P : TKC0;
     if (bm.s < 30 && (1 << bm.s) != TKC) return hipErrorInvalidValue;   // a block must own one KB-block
     dim3 grid((Ly + TKC - 1) / TKC, hx);
-    hipLaunchKernelGGL((k_z_reg<R, L, E, TKC, CI, CO, NC>), grid, dim3(TKC * P), 0, st, B, hx, Ly, Zrows, zs0, nzs,
+    TOF_LAUNCH((k_z_reg<R, L, E, TKC, CI, CO, NC>), grid, dim3(TKC * P), 0, st, B, hx, Ly, Zrows, zs0, nzs,
                        zt0, nzt, spec, prod, (const cplx<R> *)plan.tw, bm);
     return hipGetLastError();
 }
@@ -1473,7 +1439,7 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
     hipError_t e = allow_lds(k_z_pass<R>, lds);
     if (e != hipSuccess) return e;
     dim3 grid((Ly + TK - 1) / TK, hx);
-    hipLaunchKernelGGL(k_z_pass<R>, grid, dim3(kThreads), lds, st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt,
+    TOF_LAUNCH(k_z_pass<R>, grid, dim3(kThreads), lds, st, B, hx, Ly, Zrows, zs0, nzs, zt0, nzt,
                        spec, prod, forward_only ? 1 : 0, plan, TK, pitch, bm);
     return hipGetLastError();
 }
@@ -1488,10 +1454,10 @@ hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
     dim3 grid((T.ny() + 2 * NLC - 1) / (2 * NLC), T.nz());
     dim3 block((NLC / LPT) * (L / E));
     if (c == 1)
-        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, LPT, 1>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
+        TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, 1>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
                            dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
     else if (c == 3)
-        hipLaunchKernelGGL((k_xi_reg<R, L, E, NLC, LPT, 3>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
+        TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, 3>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
                            dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
     else
         return hipErrorInvalidValue;
@@ -1525,7 +1491,7 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
     hipError_t e = allow_lds(k_x_inverse<R>, lds);
     if (e != hipSuccess) return e;
     dim3 grid((T.ny() + TY - 1) / TY, T.nz());
-    hipLaunchKernelGGL(k_x_inverse<R>, grid, dim3(kThreads), lds, st, C, hx, c, T, plan,
+    TOF_LAUNCH(k_x_inverse<R>, grid, dim3(kThreads), lds, st, C, hx, c, T, plan,
                        grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, TY, pitch);
     return hipGetLastError();
 }
@@ -1535,7 +1501,7 @@ hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box
 {
     const int rows = (nz - keep.nz()) * ny + keep.nz() * (ny - keep.ny());
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_outside<R>, dim3(rows), dim3(kThreads), 0, st, a, nx, ny, nz, keep);
+    TOF_LAUNCH(k_zero_outside<R>, dim3(rows), dim3(kThreads), 0, st, a, nx, ny, nz, keep);
     return hipGetLastError();
 }
 
@@ -1547,7 +1513,7 @@ hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box s
     const long long work = (long long)c_j * ob.nx() * ob.ny() * ob.nz();
     int nb = (int)((work + kObjThreads - 1) / kObjThreads);
     nb = nb < 1 ? 1 : (nb > kObjMaxBlocks ? kObjMaxBlocks : nb);
-    hipLaunchKernelGGL(k_objective<R>, dim3(nb), dim3(kObjThreads), 0, st, kind, Hs, ob, sensor, c_j, target, lam,
+    TOF_LAUNCH(k_objective<R>, dim3(nb), dim3(kObjThreads), 0, st, kind, Hs, ob, sensor, c_j, target, lam,
                        dx, dy, vcell, h_target, J, g, partials, ticket);
     return hipGetLastError();
 }
@@ -1557,12 +1523,12 @@ hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, int nx, in
                                Box design, double alpha, unsigned long long *maxbits)
 {
     (void)nz;
-    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, maxbits, 1);
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, maxbits, 1);
     const long long n = (long long)design.nx() * design.ny() * design.nz();
     int blocks = (int)((n + kThreads - 1) / kThreads);
     blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
-    hipLaunchKernelGGL(k_absmax<R>, dim3(blocks), dim3(kThreads), 0, st, grad, nx, ny, design, maxbits);
-    hipLaunchKernelGGL(k_project<R>, dim3(blocks), dim3(kThreads), 0, st, rho, grad, nx, ny, design, alpha,
+    TOF_LAUNCH(k_absmax<R>, dim3(blocks), dim3(kThreads), 0, st, grad, nx, ny, design, maxbits);
+    TOF_LAUNCH(k_project<R>, dim3(blocks), dim3(kThreads), 0, st, rho, grad, nx, ny, design, alpha,
                        maxbits);
     return hipGetLastError();
 }
@@ -1573,7 +1539,7 @@ hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, 
     const long long n = (long long)lx * ly * lz;
     int blocks = (int)((n + 127) / 128);
     blocks = blocks > 65536 ? 65536 : blocks;
-    hipLaunchKernelGGL(k_newell_lattice, dim3(blocks), dim3(128), 0, st, c, lx, ly, lz, dx, dy, dz, lat);
+    TOF_LAUNCH(k_newell_lattice, dim3(blocks), dim3(128), 0, st, c, lx, ly, lz, dx, dy, dz, lat);
     return hipGetLastError();
 }
 
@@ -1585,7 +1551,7 @@ hipError_t launch_newell_stencil(hipStream_t st, int c, int mx, int my, int mz, 
     int blocks = (int)((n + 127) / 128);
     blocks = blocks > 65536 ? 65536 : blocks;
     const dd scale = inv_4pi_volume(dx, dy, dz);
-    hipLaunchKernelGGL(k_newell_stencil, dim3(blocks), dim3(128), 0, st, c, mx, my, mz, lx, ly, scale, lat,
+    TOF_LAUNCH(k_newell_stencil, dim3(blocks), dim3(128), 0, st, c, mx, my, mz, lx, ly, scale, lat,
                        wrapped, Lx, Ly, Lz, octant);
     return hipGetLastError();
 }
@@ -1595,12 +1561,12 @@ hipError_t launch_extract_spectrum(hipStream_t st, const cplx<double> *B, int hx
                                    double scale, R *spec, int hkz, int ky_pitch, unsigned long long *mi,
                                    unsigned long long *mr)
 {
-    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mi, 1);
-    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mr, 1);
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, mi, 1);
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, mr, 1);
     const long long n = (long long)hx * hkz * (Ly / 2 + 1);
     int blocks = (int)((n + kThreads - 1) / kThreads);
     blocks = blocks > 8192 ? 8192 : blocks;
-    hipLaunchKernelGGL(k_extract_spectrum<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Lz, scale,
+    TOF_LAUNCH(k_extract_spectrum<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Lz, scale,
                        spec, hkz, ky_pitch, mi, mr);
     return hipGetLastError();
 }
@@ -1615,16 +1581,16 @@ hipError_t launch_zsum_t(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
     dim3 grid((Ly + TKC - 1) / TKC, hx);
     constexpr int NRM = kZsumMaxRows;
     if (nzt == 1)
-        hipLaunchKernelGGL((k_zsum_gather<R, TKC, TH, CI, CO, NC, 1>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
+        TOF_LAUNCH((k_zsum_gather<R, TKC, TH, CI, CO, NC, 1>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
                            zs0, nzs, zt0, nzt, kt, prod, bm);
     else if (nzt <= NRM)
-        hipLaunchKernelGGL((k_zsum_gather<R, TKC, TH, CI, CO, NC, NRM>), grid, dim3(TKC * TH), 0, st, B, hx, Ly,
+        TOF_LAUNCH((k_zsum_gather<R, TKC, TH, CI, CO, NC, NRM>), grid, dim3(TKC * TH), 0, st, B, hx, Ly,
                            Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
     else if (nzs == 1)
-        hipLaunchKernelGGL((k_zsum_scatter<R, TKC, TH, CI, CO, NC, 1>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
+        TOF_LAUNCH((k_zsum_scatter<R, TKC, TH, CI, CO, NC, 1>), grid, dim3(TKC * TH), 0, st, B, hx, Ly, Zrows,
                            zs0, nzs, zt0, nzt, kt, prod, bm);
     else if (nzs <= NRM)
-        hipLaunchKernelGGL((k_zsum_scatter<R, TKC, TH, CI, CO, NC, NRM>), grid, dim3(TKC * TH), 0, st, B, hx, Ly,
+        TOF_LAUNCH((k_zsum_scatter<R, TKC, TH, CI, CO, NC, NRM>), grid, dim3(TKC * TH), 0, st, B, hx, Ly,
                            Zrows, zs0, nzs, zt0, nzt, kt, prod, bm);
     else
         return hipErrorInvalidValue;
@@ -1651,12 +1617,12 @@ template <typename R>
 hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Zb, int nz, double scale,
                              bool imaginary, R *kt, int ky_pitch, unsigned long long *mo, unsigned long long *mp)
 {
-    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mo, 1);
-    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, st, mp, 1);
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, mo, 1);
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, mp, 1);
     const long long n = (long long)hx * nz * Ly;
     int blocks = (int)((n + kThreads - 1) / kThreads);
     blocks = blocks > 8192 ? 8192 : blocks;
-    hipLaunchKernelGGL(k_extract_kt<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Zb, nz, scale,
+    TOF_LAUNCH(k_extract_kt<R>, dim3(blocks), dim3(kThreads), 0, st, B, hx, Ly, Zb, nz, scale,
                        imaginary ? 1 : 0, kt, ky_pitch, mo, mp);
     return hipGetLastError();
 }
@@ -1666,7 +1632,7 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                             int, const FftPlanDev &, cplx<R> *, int);                    \
     template hipError_t launch_line_fft<R>(hipStream_t, const cplx<R> *, cplx<R> *, int, int, long long, \
                                            long long, long long, long long, int, int, int, int,          \
-                                           const FftPlanDev &, bool, BlockMap, BlockMap);                \
+                                           const FftPlanDev &, bool, BlockMap, BlockMap, int, long long); \
     template hipError_t launch_z_pass<R>(hipStream_t, cplx<R> *, int, int, int, int, int, int, int,     \
                                          const SpectrumDev<R> &, const ProductDev &, bool,               \
                                          const FftPlanDev &, BlockMap);                                  \

@@ -1,0 +1,300 @@
+// Passes 2-4 fused for a convolution whose source or target spans only a few
+// z rows (the objective's plane).  With Kt, the tensor transformed along x
+// and y only, the z part of the convolution is a direct sum per (kx, ky)
+// column, out(zt) = sum_zs Kt(zt - zs) x(zs), and needs no z transform; the
+// y transforms of the many-row side can then run in the same kernel, so the
+// y spectra of those rows never go through HBM.
+//
+//   gather  (few target rows): per kx, the y FFT of every source row times
+//           Kt, summed over the source rows of a group; each group's sum is
+//           a partial spectrum row, and the inverse y pass adds the partials
+//           (in group order) before transforming.
+//   scatter (few source rows): per kx, the y FFT of the source rows (kept in
+//           LDS), then for every target row the sum against Kt and the
+//           inverse y FFT, written straight into the layout of the inverse x
+//           pass.
+//
+// A y line is held by P = L / E threads (thread p: positions p + P m, see
+// fft_reg.h); a 256-thread block runs NL = 256 / P lines side by side.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "engine.h"
+#include "fft_reg.h"
+
+namespace {
+
+using namespace tofdev;
+
+constexpr int kE = 8;           // elements per thread of a y line
+constexpr int kBlock = 256;     // threads per block
+
+// Source line of length L with data at positions [y0, y0 + ny): row[y - y0];
+// zero elsewhere and when !ok.  Addresses are clamped into the row, so the
+// loads need no branch.
+template <typename R, int L, int E>
+__device__ __forceinline__ void load_line(const cplx<R> *row, int y0, int ny, int p, bool ok, cplx<R> *v)
+{
+    constexpr int P = L / E;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int n = p + P * m;
+        const cplx<R> a = row[min(max(n - y0, 0), ny - 1)];
+        v[m] = (ok && n >= y0 && n < y0 + ny) ? a : cplx<R>{0, 0};
+    }
+}
+
+// Few target rows.  Block (kx, g) takes source rows [g rpg, (g+1) rpg) of
+// the source box; line slot l transforms rows l, l + NL, ... of that range.
+// A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][L].
+template <typename R, int L, int E, int CI, int CO, int NC, int NR>
+__global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
+                                                         int zt0, int nzt, int rpg, KtDev<R> kt, ProductDev prod,
+                                                         cplx<R> *part, const cplx<R> *table)
+{
+    constexpr int P = L / E;
+    constexpr int NL = kBlock / P;
+    constexpr int PITCH = regfft::padded_len(L);
+    constexpr int NT = regfft::twiddle_count(L, E);
+    __shared__ cplx<R> lds[NL * PITCH];
+    const int l = line_of_thread<P>();
+    const int p = threadIdx.x % P;
+    const int kx = blockIdx.x;
+    const int ra = blockIdx.y * rpg, rb = min(ra + rpg, nzs);
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    cplx<R> *my = lds + l * PITCH;
+    cplx<R> acc[NR][E][CO];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+#pragma unroll
+            for (int o = 0; o < CO; ++o) acc[r][m][o] = cplx<R>{0, 0};
+    // the same trip count in every slot: the transforms hold block barriers
+    const int nit = (rb - ra + NL - 1) / NL;
+    for (int it = 0; it < nit; ++it) {
+        const int zr = ra + it * NL + l;
+        const bool ok = zr < rb;
+        const int zrc = min(zr, rb - 1);
+        // tensor values (independent of the transform) and the lines, all loads first;
+        // a row past the range transforms zeros
+        R K[E][NR][NC];
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                kt_at<R, NC>(kt, prod, kx, p + P * m, zt0 + min(r, nzt - 1) - (zs0 + zrc), K[m][r]);
+        cplx<R> X[CI][E];
+#pragma unroll
+        for (int i = 0; i < CI; ++i)
+            load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + zrc) * nys, ys0, nys, p, ok, X[i]);
+#pragma unroll
+        for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E>(X[i], tw, my, p, false);
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            cplx<R> xm[CI];
+#pragma unroll
+            for (int i = 0; i < CI; ++i) xm[i] = X[i][m];
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nzt) zsum_mac<R, CI, CO, NC>(prod, K[m][r], xm, acc[r][m]);
+        }
+    }
+    // the slots' sums, added in slot order
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r >= nzt) break;
+#pragma unroll
+        for (int o = 0; o < CO; ++o) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < E; ++m) my[p + P * m] = acc[r][m][o];
+            __syncthreads();
+            cplx<R> *dst = part + (((long long)(blockIdx.y * CO + o) * hx + kx) * nzt + r) * L;
+            for (int q = threadIdx.x; q < L; q += kBlock) {
+                cplx<R> s = lds[q];
+                for (int sl = 1; sl < NL; ++sl) s = cadd(s, lds[sl * PITCH + q]);
+                dst[q] = s;
+            }
+        }
+    }
+}
+
+// Few source rows.  Block (kx, g) takes target rows [g rpg, (g+1) rpg) of
+// the target box; line slot l handles rows l, l + NL, ... of that range.
+// A is [CI][hx][nzs][nys]; C is [CO][hx][nzt][nyt] with y from yt0 (the
+// input layout of the inverse x pass).
+template <typename R, int L, int E, int CI, int CO, int NC, int NR>
+__global__ __launch_bounds__(kBlock) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
+                                                          int zt0, int nzt, int rpg, int yt0, int nyt, KtDev<R> kt,
+                                                          ProductDev prod, cplx<R> *C, const cplx<R> *table)
+{
+    constexpr int P = L / E;
+    constexpr int NL = kBlock / P;
+    constexpr int PITCH = regfft::padded_len(L);
+    constexpr int NT = regfft::twiddle_count(L, E);
+    constexpr int NQ = NR * CI;
+    __shared__ cplx<R> lds[NL * PITCH];
+    __shared__ cplx<R> xs[NQ * L];   // source spectra, line q = r CI + i
+    const int l = line_of_thread<P>();
+    const int p = threadIdx.x % P;
+    const int kx = blockIdx.x;
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    cplx<R> *my = lds + l * PITCH;
+    const int nq = nzs * CI;
+#pragma unroll
+    for (int b = 0; b < (NQ + NL - 1) / NL; ++b) {
+        const int q = b * NL + l;
+        const bool ok = q < nq;
+        const int qc = min(q, nq - 1);
+        const int r = qc / CI, i = qc % CI;
+        cplx<R> v[E];
+        load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + r) * nys, ys0, nys, p, ok, v);
+        regfft::fft_line<R, L, E>(v, tw, my, p, false);
+        if (ok) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) xs[q * L + p + P * m] = v[m];
+        }
+    }
+    __syncthreads();
+    const int ra = blockIdx.y * rpg, rb = min(ra + rpg, nzt);
+    const int nit = (rb - ra + NL - 1) / NL;
+    for (int it = 0; it < nit; ++it) {
+        const int zr = ra + it * NL + l;
+        const bool ok = zr < rb;
+        const int zrc = min(zr, rb - 1);
+        R K[E][NR][NC];
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                kt_at<R, NC>(kt, prod, kx, p + P * m, zt0 + zrc - (zs0 + min(r, nzs - 1)), K[m][r]);
+        cplx<R> Y[CO][E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            cplx<R> out[CO];
+#pragma unroll
+            for (int o = 0; o < CO; ++o) out[o] = cplx<R>{0, 0};
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (r >= nzs) break;
+                cplx<R> xm[CI];
+#pragma unroll
+                for (int i = 0; i < CI; ++i) xm[i] = xs[(r * CI + i) * L + p + P * m];
+                zsum_mac<R, CI, CO, NC>(prod, K[m][r], xm, out);
+            }
+#pragma unroll
+            for (int o = 0; o < CO; ++o) Y[o][m] = out[o];
+        }
+#pragma unroll
+        for (int o = 0; o < CO; ++o) {
+            regfft::fft_line<R, L, E>(Y[o], tw, my, p, true);
+            if (ok) {
+                cplx<R> *dst = C + (((long long)o * hx + kx) * nzt + zrc) * nyt - yt0;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int n = p + P * m;
+                    if (n >= yt0 && n < yt0 + nyt) dst[n] = Y[o][m];
+                }
+            }
+        }
+    }
+}
+
+// Register and LDS limits of the fused kernels: the gather keeps NR x CO
+// accumulators per element, both keep NR x NC tensor values per element, the
+// scatter keeps NR x CI source spectra in LDS.
+constexpr bool gather_fits(int CO, int NC, int NR) { return NR * CO <= 4 && NR * NC <= 6; }
+constexpr size_t scatter_lds(int L, int CI, int NR, size_t csz)
+{
+    return ((size_t)(kBlock / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
+}
+constexpr bool scatter_fits(int L, int CI, int NC, int NR, size_t csz)
+{
+    return NR * NC <= 6 && scatter_lds(L, CI, NR, csz) <= 64 * 1024;
+}
+
+template <typename R, int L, int CI, int CO, int NC>
+hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
+                          const ProductDev &prod, const cplx<R> *table, bool check_only)
+{
+    constexpr int NRM = kZsumMaxRows;
+    constexpr size_t csz = sizeof(cplx<R>);
+    const int G = (rows + a.rpg - 1) / a.rpg;
+    const dim3 grid(a.hx, G);
+    if (a.nzt <= NRM) {
+        if (a.nzt == 1) {
+            if constexpr (gather_fits(CO, NC, 1)) {
+                if (check_only) return hipSuccess;
+                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+                                   a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
+                return hipGetLastError();
+            }
+        } else {
+            if constexpr (gather_fits(CO, NC, NRM)) {
+                if (check_only) return hipSuccess;
+                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+                                   a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
+                return hipGetLastError();
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    if (a.nzs == 1) {
+        if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
+            if (check_only) return hipSuccess;
+            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table);
+            return hipGetLastError();
+        }
+    } else if (a.nzs <= NRM) {
+        if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
+            if (check_only) return hipSuccess;
+            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int L>
+hipError_t launch_yzsum_c(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
+                          const ProductDev &prod, const cplx<R> *table, bool check_only)
+{
+    const int key = prod.c_in * 4 + prod.c_out;
+    if (key == 5 && prod.nc == 1) return launch_yzsum_l<R, L, 1, 1, 1>(st, a, rows, kt, prod, table, check_only);
+    switch (key) {
+    case 5: return launch_yzsum_l<R, L, 1, 1, 6>(st, a, rows, kt, prod, table, check_only);
+    case 7: return launch_yzsum_l<R, L, 1, 3, 6>(st, a, rows, kt, prod, table, check_only);
+    case 13: return launch_yzsum_l<R, L, 3, 1, 6>(st, a, rows, kt, prod, table, check_only);
+    case 15: return launch_yzsum_l<R, L, 3, 3, 6>(st, a, rows, kt, prod, table, check_only);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_yz_sum(hipStream_t st, const YzSumArgs<R> &a, const KtDev<R> &kt, const ProductDev &prod,
+                         const FftPlanDev &plan, bool check_only)
+{
+    if (a.rpg < 1 || a.nzs < 1 || a.nzt < 1 || a.nys < 1 || a.nyt < 1) return hipErrorInvalidValue;
+    const int rows = a.nzt <= kZsumMaxRows ? a.nzs : a.nzt;
+    const cplx<R> *table = (const cplx<R> *)plan.tw;
+    switch (plan.L) {
+    case 32: return launch_yzsum_c<R, 32>(st, a, rows, kt, prod, table, check_only);
+    case 64: return launch_yzsum_c<R, 64>(st, a, rows, kt, prod, table, check_only);
+    case 128: return launch_yzsum_c<R, 128>(st, a, rows, kt, prod, table, check_only);
+    case 256: return launch_yzsum_c<R, 256>(st, a, rows, kt, prod, table, check_only);
+    case 512: return launch_yzsum_c<R, 512>(st, a, rows, kt, prod, table, check_only);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_yz_sum<float>(hipStream_t, const YzSumArgs<float> &, const KtDev<float> &,
+                                         const ProductDev &, const FftPlanDev &, bool);
+template hipError_t launch_yz_sum<double>(hipStream_t, const YzSumArgs<double> &, const KtDev<double> &,
+                                          const ProductDev &, const FftPlanDev &, bool);

@@ -23,14 +23,13 @@ STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TO
 EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "tof_field",
            "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
            "tof_padded_lengths", "tof_workspace_bytes", "tof_last_error", "tof_dd_newell_host",
-           "tof_profile_enable", "tof_profile_read"]
+           "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option"]
+
+OPT_ZSUM, OPT_FUSE_YZ = 1, 2
 
 PROFILE_SLOTS = 12
 PROFILE_NAMES = ["fwd_x", "fwd_y", "fwd_z_product", "fwd_inv_y", "fwd_inv_x_field", "objective",
                  "adj_x", "adj_y", "adj_z_product", "adj_inv_y", "adj_inv_x_grad", "zero_fill"]
-# kernel symbol of each slot (as rocprofv3 names it, without template arguments)
-PROFILE_KERNELS = ["k_x_forward", "k_line_fft", "k_z_pass", "k_line_fft", "k_x_inverse", "k_objective",
-                   "k_x_forward", "k_line_fft", "k_z_pass", "k_line_fft", "k_x_inverse", "k_zero_outside"]
 
 
 class TofError(RuntimeError):
@@ -86,9 +85,12 @@ def lib():
         L.tof_dd_newell_host.restype = dbl
         L.tof_profile_enable.argtypes = [vp, i32]
         L.tof_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
+        L.tof_profile_kernel.argtypes = [vp, i32]
+        L.tof_profile_kernel.restype = ctypes.c_char_p
+        L.tof_set_option.argtypes = [vp, i32, i32]
         for name in ("tof_create", "tof_set_design", "tof_set_objective", "tof_field",
                      "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
-                     "tof_padded_lengths", "tof_profile_enable", "tof_profile_read"):
+                     "tof_padded_lengths", "tof_profile_enable", "tof_profile_read", "tof_set_option"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -218,6 +220,14 @@ class Engine:
         by = (ctypes.c_double * PROFILE_SLOTS)()
         self._check(lib().tof_profile_read(self._ctx, ms, cnt, by))
         return [(PROFILE_NAMES[i], ms[i], cnt[i], by[i]) for i in range(PROFILE_SLOTS)]
+
+    def profile_kernels(self):
+        """Per slot: the name of the kernel last timed there ("" if none)."""
+        return [lib().tof_profile_kernel(self._ctx, i).decode() for i in range(PROFILE_SLOTS)]
+
+    def set_option(self, option: int, value: bool):
+        """Pass choice (OPT_ZSUM, OPT_FUSE_YZ); see tof_set_option."""
+        self._check(lib().tof_set_option(self._ctx, int(option), 1 if value else 0))
 
     def padded_lengths(self) -> Tuple[int, int, int]:
         out = (ctypes.c_int32 * 3)()

@@ -49,6 +49,30 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+# pass choices: y transforms fused with the direct z sum, the direct z sum
+# alone, FFTs along z (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ)
+PATHS = {"fused": (1, 1), "zsum": (1, 0), "zfft": (0, 0)}
+
+
+def engine_on_path(w, dtype, path):
+    t = tof()
+    e = t.engine_for(w, dtype)
+    zsum, fuse = PATHS[path]
+    e.set_option(t.OPT_ZSUM, zsum)
+    e.set_option(t.OPT_FUSE_YZ, fuse)
+    return e
+
+
+_ORACLE = {}
+
+
+def cached(key, fn):
+    """Oracle results shared by the parametrizations of one case."""
+    if key not in _ORACLE:
+        _ORACLE[key] = fn()
+    return _ORACLE[key]
+
+
 # ---------------------------------------------------------------- tensor setup
 @pytest.mark.parametrize("n,h", [((12, 10, 14), (1.0, 1.0, 1.0)), ((9, 11, 8), (0.7, 1.3, 0.9)),
                                  ((64, 64, 64), (1.0, 1.0, 0.5))])
@@ -69,22 +93,24 @@ FIELD_CASES = [
     ("vector_m0", lambda: wl.small_random(22, n=(9, 12, 10), varying_m0=True)),
     ("tilted_m0", lambda: wl.small_random(23, n=(10, 9, 11), m0=(0.3, -0.4, 0.866))),
     ("nonsmooth", lambda: wl.small_random(24, n=(11, 13, 6), h=(1.0, 1.0, 1.0))),  # 2n = 22, 26: L = 24, 28
+    # two design rows, Ly = 32: the few-source-row paths
+    ("thin_design", lambda: wl.small_random(25, n=(11, 16, 9), design=(1, 10, 0, 16, 2, 4))),
 ]
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("name,make", FIELD_CASES)
-def test_gpu_field_matches_direct_sum(torch, name, make, dtype):
+def test_gpu_field_matches_direct_sum(torch, name, make, dtype, path):
     w = make()
-    say("field", name, dtype, w.n)
-    t = tof()
-    e = t.engine_for(w, dtype)
+    say("field", name, dtype, path, w.n)
+    e = engine_on_path(w, dtype, path)
     tdt = e.dtype
     H = host(e.field(dev(torch, w.rho, tdt), comps=7))
     torch.cuda.synchronize()
     nx, ny, nz = w.n
-    ref = oracle.field(w.n, w.h, oracle.magnetization(w), w.design, (0, nx, 0, ny, 0, nz),
-                       oracle.m0_mask(w), 7)
+    ref = cached(("field", name), lambda: oracle.field(w.n, w.h, oracle.magnetization(w), w.design,
+                                                       (0, nx, 0, ny, 0, nz), oracle.m0_mask(w), 7))
     assert rel_inf(H, ref) <= TOL[dtype], rel_inf(H, ref)
     # single components in component order
     Hz = host(e.field(dev(torch, w.rho, tdt), comps=4))
@@ -106,20 +132,25 @@ GRAD_CASES = [
     ("mean_sq_hz_corner", lambda: wl.small_random(35, n=(8, 8, 9), j_kind=wl.J_MEAN_SQ_HZ,
                                                   sensor=(0, 3, 5, 8, 8, 9))),
     ("p1_single_design_cell", lambda: wl.small_random(36, n=(7, 6, 8), p=1, design=(3, 4, 2, 3, 1, 2))),
+    # three sensor rows with Ly = 32: the fused kernels' multi-row variants
+    ("sensor3_pow2y", lambda: wl.small_random(37, n=(19, 16, 13), sensor=(6, 12, 5, 11, 10, 13))),
+    # varying M0 and a vector target with Ly = 64: three components in and out
+    ("vector_pow2y", lambda: wl.small_random(38, n=(12, 32, 10), j_kind=wl.J_MEAN_SQ_H_TARGET, varying_m0=True)),
 ]
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("name,make", GRAD_CASES)
-def test_gpu_objective_and_grad_match_oracle(torch, name, make, dtype):
+def test_gpu_objective_and_grad_match_oracle(torch, name, make, dtype, path):
     w = make()
-    say("grad", name, dtype, w.n)
-    e = tof().engine_for(w, dtype)
+    say("grad", name, dtype, path, w.n)
+    e = engine_on_path(w, dtype, path)
     J, g = e.objective_and_grad(dev(torch, w.rho, e.dtype))
     torch.cuda.synchronize()
     J = float(J.item())
     g = host(g)
-    Jr, gr, _ = oracle.objective_and_grad(w)
+    Jr, gr, _ = cached(("grad", name), lambda: oracle.objective_and_grad(w))
     assert abs(J - Jr) <= TOL[dtype] * abs(Jr), (J, Jr)
     assert rel_inf(g, gr) <= TOL[dtype], rel_inf(g, gr)
     # zero outside the design region
