@@ -179,9 +179,10 @@ tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream);
  * Per-launch timing (a measurement aid).  While enabled, every hot call
  * brackets each kernel launch with HIP events on its launch stream.  Slots:
  * 0-4 the passes of the forward convolution (x, y, z with the tensor product,
- * inverse y, inverse x with its epilogue), 5 the objective, 6-10 the passes of
- * the adjoint convolution, 11 the zero fill of the gradient outside the design
- * region.  With the fused y / z-sum kernels (TOF_OPT_FUSE_YZ) slot 2 (8 in
+ * inverse y, inverse x with its epilogue), 5 the objective (with
+ * TOF_OPT_FUSE_OBJECTIVE also the adjoint's x pass, slot 6 then unused), 6-10
+ * the passes of the adjoint convolution (the last one also zeroes the
+ * gradient outside the design region), 11 reserved.  With the fused y / z-sum kernels (TOF_OPT_FUSE_YZ) slot 2 (8 in
  * the adjoint) holds the fused kernel, slot 1 (7) is unused, and slot 3 (9)
  * holds the inverse y pass after a gather and is unused after a scatter.  At most 1024 calls are recorded between reads; later ones are not
  * timed.  Errors: TOF_ERR_INVALID, TOF_ERR_HIP.
@@ -214,10 +215,16 @@ const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot);
  *   TOF_OPT_FUSE_YZ  that direct sum runs fused with the y transforms
  *                    (power-of-two Ly from 32 to 512), so the y spectra of
  *                    the many-row side never go through device memory.
+ *   TOF_OPT_FUSE_OBJECTIVE  tof_objective_and_grad evaluates J and dJ/dH in
+ *                    the kernel that starts the adjoint (its FFT along x;
+ *                    power-of-two Lx from 32 to 512), so dJ/dH is never
+ *                    stored.  The J reduction order differs from the
+ *                    separate objective kernel's (rounding only).
  * Errors: TOF_ERR_INVALID.
  */
 #define TOF_OPT_ZSUM 1
 #define TOF_OPT_FUSE_YZ 2
+#define TOF_OPT_FUSE_OBJECTIVE 3
 tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value);
 
 /* Padded lengths chosen for the context: out[0..2] = Lx, Ly, Lz. */

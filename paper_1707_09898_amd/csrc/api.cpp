@@ -85,6 +85,7 @@ struct tof_ctx {
     // pass choices (tof_set_option)
     bool opt_zsum = true;    // direct z sum against Kt for few source / target rows
     bool opt_fuse = true;    // that sum fused with the y transforms
+    bool opt_fuse_obj = true;   // the objective fused with the adjoint's x pass
     std::string err;
 };
 
@@ -250,8 +251,10 @@ void finish_product(ProductDev &pr)
 template <typename R>
 tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const DesignDev<R> &dsg,
                     View4<const R> src, Box S, Box T, const ProductDev &prod, bool grad_epi, View4<R> out,
-                    const R *m0u, R *grad)
+                    const R *m0u, R *grad, bool a_ready = false)
 {
+    // the gradient epilogue (T = design box) also zeroes the gradient outside the design box
+    const bool zero_rest = grad_epi;
     const bool f64 = sizeof(R) == 8;
     const FftPlanDev plx = ctx->px.dev(f64), ply = ctx->py.dev(f64), plz = ctx->pz.dev(f64);
     cplx<R> *A = (cplx<R> *)ctx->A.p, *B = (cplx<R> *)ctx->B.p, *C = (cplx<R> *)ctx->C.p;
@@ -270,11 +273,15 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
     for (int c = 0; c < 6; ++c) ncomp += prod.need >> c & 1;
     const double spec_bytes = ncomp * (double)hx * ctx->hkz * (Ly / 2 + 1) * w;
     const double nTrow = (double)T.ny() * T.nz();
-    const double x_out = grad_epi ? nTrow * ctx->nx * w * (2.0 + (dsg.m0f ? 3.0 : 0.0))
+    const Box &d = dsg.design;
+    const double zero_bytes = zero_rest ? ((double)ctx->nx * ctx->ny * ctx->nz - (double)ctx->nx * d.ny() * d.nz()) * w : 0.0;
+    const double x_out = grad_epi ? nTrow * ctx->nx * w * (2.0 + (dsg.m0f ? 3.0 : 0.0)) + zero_bytes
                                   : prod.c_out * nTrow * T.nx() * w;
-    HIP_TRY(ctx, timed(ctx, st, slot0 + 0, src_bytes + a_elems * cw, [&] {
-        return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx);
-    }));
+    if (!a_ready) {   // else the caller's kernel has written the x pass output into A
+        HIP_TRY(ctx, timed(ctx, st, slot0 + 0, src_bytes + a_elems * cw, [&] {
+            return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx);
+        }));
+    }
     const bool zsum_counts = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
     const bool few = ctx->opt_zsum && zsum_counts && (S.nz() <= kZsumMaxRows || T.nz() <= kZsumMaxRows);
     KtDev<R> kt{(const R *)ctx->kt.p, ctx->comp_stride_kt, ctx->nz, ctx->kt_pitch};
@@ -293,8 +300,10 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         G = (rows + ya.rpg - 1) / ya.rpg;
         if (launch_yz_sum<R>(st, ya, kt, prod, ply, true) == hipSuccess) {
             const double part_bytes = (double)G * part_rows * cw;
+            // the fused kernels read Kt for ky <= Ly/2 only (parity in y gives the rest)
+            const double kt_half = ncomp * (double)hx * drows * (Ly / 2 + 1) * w;
             if (gather) {
-                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_bytes + part_bytes, [&] {
+                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_half + part_bytes, [&] {
                     return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
                 }));
                 const BlockMap flat{30, 0, 0};
@@ -304,12 +313,12 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                                               flat, G, part_rows);
                 }));
             } else {
-                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_bytes + c_elems * cw, [&] {
+                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_half + c_elems * cw, [&] {
                     return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
                 }));
             }
             HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
-                return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad);
+                return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest);
             }));
             return TOF_OK;
         }
@@ -335,7 +344,7 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                                   (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true, bm, plain);
     }));
     HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
-        return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad);
+        return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest);
     }));
     return TOF_OK;
 }
@@ -401,20 +410,14 @@ int popcount3(int m) { return (m & 1) + (m >> 1 & 1) + (m >> 2 & 1); }
 
 template <typename R>
 tof_status adjoint_to_grad(tof_ctx *ctx, hipStream_t st, const void *rho, View4<const R> src, Box S,
-                           int comps_mask, void *grad)
+                           int comps_mask, void *grad, bool a_ready = false)
 {
     DesignDev<R> dsg = design_dev<R>(ctx, rho);
     ProductDev pr = adjoint_product(ctx, comps_mask);
     const R one[3] = {(R)1, (R)0, (R)0};
     View4<R> none{};
-    tof_status s = convolve<R>(ctx, st, 6, SRC_ARRAY, dsg, src, S, ctx->design, pr, true, none, one, (R *)grad);
-    if (s != TOF_OK) return s;
-    const Box d = ctx->design;
-    const double zbytes = ((double)ctx->nx * ctx->ny * ctx->nz - (double)ctx->nx * d.ny() * d.nz()) * sizeof(R);
-    HIP_TRY(ctx, timed(ctx, st, 11, zbytes, [&] {
-        return launch_zero_outside<R>(st, (R *)grad, ctx->nx, ctx->ny, ctx->nz, ctx->design);
-    }));
-    return TOF_OK;
+    // the last pass also zeroes the gradient outside the design box
+    return convolve<R>(ctx, st, 6, SRC_ARRAY, dsg, src, S, ctx->design, pr, true, none, one, (R *)grad, a_ready);
 }
 
 template <typename R>
@@ -446,6 +449,22 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
     tof_status s = convolve<R>(ctx, st, 0, ctx->m0f ? SRC_RHO_VECTOR : SRC_RHO_SCALAR, dsg, nosrc, ctx->design,
                                ob, pf, false, hs, zero3, nullptr);
     if (s != TOF_OK) return s;
+    if (ctx->opt_fuse_obj) {
+        // the objective fused with the adjoint's x pass: dJ/dH goes straight into A
+        ObjectiveDev<R> o{ctx->kind, (const R *)ctx->Hs.p, ob, ctx->sensor, cj, nob,
+                          ctx->sensor.nx() * ctx->sensor.ny() * ctx->sensor.nz(), ctx->target, ctx->lam, ctx->dx,
+                          ctx->dy, ctx->dx * ctx->dy * ctx->dz, (const double *)ctx->Ht.p, J,
+                          (double *)ctx->partials.p, (unsigned int *)ctx->ticket.p};
+        const FftPlanDev plx = ctx->px.dev(sizeof(R) == 8);
+        cplx<R> *A = (cplx<R> *)ctx->A.p;
+        if (launch_objective_xf<R>(st, o, plx, A, ctx->hx, true) == hipSuccess) {
+            const double ht_bytes = ctx->kind == TOF_J_MEAN_SQ_H_TARGET ? 3.0 * o.S * 8.0 : 0.0;
+            const double fbytes = cj * nob * sizeof(R) + ht_bytes + 2.0 * sizeof(R) * cj * ctx->hx * ob.nz() * ob.ny();
+            HIP_TRY(ctx, timed(ctx, st, 5, fbytes, [&] { return launch_objective_xf<R>(st, o, plx, A, ctx->hx, false); }));
+            View4<const R> nosrc2{};
+            return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true);
+        }
+    }
     const double obytes = 2.0 * cj * nob * sizeof(R);
     HIP_TRY(ctx, timed(ctx, st, 5, obytes, [&] {
         return launch_objective<R>(st, ctx->kind, (const R *)ctx->Hs.p, ob, ctx->sensor, cj, ctx->target, ctx->lam,
@@ -640,7 +659,7 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
     if ((s = dev_alloc(ctx, ctx->ticket, 64)) != TOF_OK) return bail(s);
     {
         hipError_t e0 = hipMemsetAsync(ctx->ticket.p, 0, 64, st);
-        if (e0 != hipSuccess) return bail(hip_fail(ctx, e0, "hipMemsetAsync(ticket)"));
+        if (e0 != hipSuccess) return bail(hip_fail(ctx, e0, "hipMemsetAsync(counters)"));
     }
     if ((s = compute_spectra(ctx, st)) != TOF_OK) return bail(s);
     hipError_t e = hipStreamSynchronize(st);
@@ -836,6 +855,7 @@ tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value)
     switch (option) {
     case TOF_OPT_ZSUM: ctx->opt_zsum = value != 0; return TOF_OK;
     case TOF_OPT_FUSE_YZ: ctx->opt_fuse = value != 0; return TOF_OK;
+    case TOF_OPT_FUSE_OBJECTIVE: ctx->opt_fuse_obj = value != 0; return TOF_OK;
     default: return fail(ctx, TOF_ERR_INVALID, "unknown option");
     }
 }

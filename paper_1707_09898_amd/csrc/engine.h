@@ -158,16 +158,41 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                              bool imaginary, R *kt, int ky_pitch, unsigned long long *other_max_bits,
                              unsigned long long *part_max_bits);
 
+// zero_outside (with the gradient epilogue, T the design box): also zero the
+// gradient rows outside the design box, in the same launch where possible.
 template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
-                            const DesignDev<R> &dsg, const R *m0u, R *grad);
-
-template <typename R>
-hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box keep);
+                            const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside);
 
 // blocks the objective kernel may use (partials buffer length)
 constexpr int kObjMaxBlocks = 1024;
+
+// The objective's inputs and outputs on the device.
+template <typename R>
+struct ObjectiveDev {
+    int kind;
+    const R *Hs;          // [c_j][ob] field on the objective box
+    Box ob, sb;           // objective box (sensor grown by the stencil), sensor box
+    int c_j;              // field components J reads (1: Hz; 3: Hx, Hy, Hz)
+    long long nob;        // cells of ob
+    int S;                // sensor cells
+    double t, lam, dx, dy, vcell;
+    const double *ht;     // [3][sb] target field (kind 3)
+    double *J;            // J (one double)
+    double *partials;     // kObjMaxBlocks block sums
+    unsigned int *ticket; // completion counter, 0 between launches
+};
+
+// The objective fused with the first pass of the adjoint: per row pair of ob,
+// dJ/dH from Hs, the J terms of its sensor cells (block sums added in block
+// order by the last block), and the real-to-complex FFT along x of dJ/dH into
+// A ([c_j][hx][ob.nz][ob.ny], the x-pass layout with source box ob).  Needs a
+// power-of-two Lx in [32, 512] and at most kObjMaxBlocks row pairs, else
+// hipErrorInvalidValue; check_only: report, launch nothing.
+template <typename R>
+hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
+                              bool check_only);
 
 template <typename R>
 hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,

@@ -48,6 +48,24 @@ constexpr int twiddle_count(int L, int E)
     return n;
 }
 
+// Ordering of the exchange through LDS.  A line whose P threads lie in one
+// wave (threads l P .. l P + P - 1 with P dividing 64) needs no block
+// barrier: a wave's LDS accesses are performed in issue order, so a fence
+// that keeps the compiler from reordering them is enough, and the waves of a
+// block then run their lines independently.  Lines spread over several waves
+// use the block barrier.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void dft16(cplx<R> *v, bool inv)
 {
@@ -122,7 +140,7 @@ __device__ __forceinline__ void load_twiddles(const cplx<R> *table, int p, cplx<
 }
 
 // One stage S of the transform (S = 0 .. num_stages - 1), then the rest.
-template <typename R, int L, int E, int S>
+template <typename R, int L, int E, int S, bool WAVE>
 __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R> *lds, int p, bool inv)
 {
     constexpr int P = L / E;
@@ -162,23 +180,26 @@ __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R
             }
         }
         if constexpr (!last) {
-            __syncthreads();
+            exchange_sync<WAVE>();
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = lds[swz(p + P * m)];
-            __syncthreads();
-            fft_stages<R, L, E, S + 1>(v, tw, lds, p, inv);
+            exchange_sync<WAVE>();
+            fft_stages<R, L, E, S + 1, WAVE>(v, tw, lds, p, inv);
         }
     }
 }
 
 // Transform one line held as v[m] = x[p + P m] by thread p.  `lds` is this
-// line's exchange area (padded_len(L) complex; position i at swz(i)).  All threads of the
-// block call it together (it contains block barriers).  On return v[m] holds
-// X[p + P m].  Forward: exp(-2 pi i jk/L); inverse: exp(+2 pi i jk/L), unscaled.
-template <typename R, int L, int E>
+// line's exchange area (padded_len(L) complex; position i at swz(i)).  With
+// WAVE false all threads of the block call it together (it contains block
+// barriers); with WAVE true the line's threads must be P consecutive threads
+// of one wave (see exchange_sync).  On return v[m] holds X[p + P m].
+// Forward: exp(-2 pi i jk/L); inverse: exp(+2 pi i jk/L), unscaled.
+template <typename R, int L, int E, bool WAVE = false>
 __device__ __forceinline__ void fft_line(cplx<R> *v, const cplx<R> *tw, cplx<R> *lds, int p, bool inv)
 {
-    fft_stages<R, L, E, 0>(v, tw, lds, p, inv);
+    static_assert(!WAVE || 64 % (L / E) == 0, "a wave-synchronized line must lie inside one wave");
+    fft_stages<R, L, E, 0, WAVE>(v, tw, lds, p, inv);
 }
 
 }  // namespace regfft

@@ -358,24 +358,43 @@ __global__ __launch_bounds__(kThreads) void k_x_inverse(const cplx<R> *C, int hx
 // Zero the x rows (y, z) outside keep.y x keep.z: first the whole layers with
 // z outside keep.z, then the rows of the kept layers with y outside keep.y.
 // Block b writes one row.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_zero_outside(R *a, int nx, int ny, int nz, Box keep)
+// Row q of the (z, y) rows outside `keep` (x spans the grid): first the
+// layers outside keep's z range, then the rows of keep's layers outside its
+// y range.  There are (nz - keep.nz) ny + keep.nz (ny - keep.ny) of them.
+__device__ __forceinline__ void outside_row(int q, int ny, const Box &keep, int &y, int &z)
 {
-    const int b = blockIdx.x;
     const int dz = keep.z1 - keep.z0, dy = keep.y1 - keep.y0;
-    const int n_layer_rows = (nz - dz) * ny;
-    int y, z;
-    if (b < n_layer_rows) {
-        const int l = b / ny;
-        y = b % ny;
-        z = l < keep.z0 ? l : keep.z1 + (l - keep.z0);
-    } else {
-        const int q = b - n_layer_rows;
-        const int oy = ny - dy;
+    const int below = keep.z0 * ny;
+    if (q < below) {
+        z = q / ny;
+        y = q % ny;
+        return;
+    }
+    q -= below;
+    const int oy = ny - dy;
+    if (q < dz * oy) {
         z = keep.z0 + q / oy;
         const int yy = q % oy;
         y = yy < keep.y0 ? yy : keep.y1 + (yy - keep.y0);
+        return;
     }
+    q -= dz * oy;
+    z = keep.z1 + q / ny;
+    y = q % ny;
+}
+
+__host__ __device__ constexpr long long outside_rows(int ny, int nz, const Box &keep)
+{
+    return (long long)(nz - keep.nz()) * ny + (long long)keep.nz() * (ny - keep.ny());
+}
+
+constexpr int kZeroRowsPerBlock = 8;
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_zero_outside(R *a, int nx, int ny, int nz, Box keep)
+{
+    int y, z;
+    outside_row(blockIdx.x, ny, keep, y, z);
     R *row = a + ((long long)z * ny + y) * nx;
     for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = (R)0;
 }
@@ -488,12 +507,162 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
         last = atomicAdd(ticket, 1u) == (unsigned int)(nb - 1);
     }
     __syncthreads();
-    if (last && threadIdx.x == 0) {
+    if (last) {
+        // the block sums into LDS by all threads at once, then added in block order
+        __shared__ double sums[kObjMaxBlocks];
         __threadfence();
-        double total = 0.0;
-        for (int b = 0; b < nb; ++b) total += ((volatile double *)partials)[b];
-        if (J) *J = (kind == 4) ? -0.5 * vcell * total : total / (double)S;
-        *ticket = 0u;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) sums[b] = partials[b];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double total = 0.0;
+            for (int b = 0; b < nb; ++b) total += sums[b];
+            if (J) *J = (kind == 4) ? -0.5 * vcell * total : total / (double)S;
+            *ticket = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The objective fused with the adjoint's x pass (see launch_objective_xf).
+
+// dJ/dH_cc at the objective-box cell (x, y, z), and in jterm the cell's term
+// of J's sum (zero off the sensor); the same discrete J as k_objective.  H(x, y)
+// returns component cc of the field at (x, y, z) for any (x, y) of ob.
+template <typename R, typename HF>
+__device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int cc, int x, int y, int z, HF H,
+                                                 double &jterm)
+{
+    const Box &sb = o.sb;
+    const bool in = sb.has(x, y, z);
+    const double invS = 1.0 / (double)o.S;
+    const double h = H(x, y);
+    if (o.kind == 3) {
+        const int s = in ? ((z - sb.z0) * sb.ny() + (y - sb.y0)) * sb.nx() + (x - sb.x0) : 0;
+        const double d = h - o.ht[(long long)cc * o.S + s];
+        jterm = in ? d * d : 0.0;
+        return in ? 2.0 * d * invS : 0.0;
+    }
+    if (o.kind == 4) {
+        jterm = in ? h * h : 0.0;
+        return in ? -o.vcell * h : 0.0;
+    }
+    const double d = h - o.t;
+    double v = in ? 2.0 * d * invS : 0.0;
+    jterm = in ? d * d : 0.0;
+    if (o.kind == 2) {
+        // central differences at this cell (its J term) and at the four sensor
+        // neighbours whose differences read this cell (the transpose)
+        const double gx = (H(x + 1, y) - H(x - 1, y)) / (2.0 * o.dx);
+        const double gy = (H(x, y + 1) - H(x, y - 1)) / (2.0 * o.dy);
+        if (in) jterm += o.lam * (gx * gx + gy * gy);
+        const double cxs = o.lam * invS / o.dx, cys = o.lam * invS / o.dy;
+        if (sb.has(x - 1, y, z)) v += cxs * ((h - H(x - 2, y)) / (2.0 * o.dx));
+        if (sb.has(x + 1, y, z)) v -= cxs * ((H(x + 2, y) - h) / (2.0 * o.dx));
+        if (sb.has(x, y - 1, z)) v += cys * ((h - H(x, y - 2)) / (2.0 * o.dy));
+        if (sb.has(x, y + 1, z)) v -= cys * ((H(x, y + 2) - h) / (2.0 * o.dy));
+    }
+    return v;
+}
+
+// Block: one row pair (y, y + 1) of ob at one z, one component; P threads.
+template <typename R, int L, int E>
+__global__ __launch_bounds__(L / E) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
+                                                        const cplx<R> *table)
+{
+    constexpr int P = L / E;
+    constexpr int PITCH = regfft::padded_len(L);
+    constexpr int NT = regfft::twiddle_count(L, E);
+    __shared__ cplx<R> lds[PITCH];
+    __shared__ double red[P];
+    __shared__ bool last;
+    constexpr int TR = 6;   // tile rows: the pair and two more on each side (the stencil's reach)
+    __shared__ R tile[TR * L];
+    const Box &ob = o.ob;
+    const int p = threadIdx.x;
+    const int cc = blockIdx.z;
+    const int zrel = blockIdx.y;
+    const int z = ob.z0 + zrel;
+    const int ybase = ob.y0 + 2 * blockIdx.x;
+    const bool two = ybase + 1 < ob.y1;
+    cplx<R> tw[NT > 0 ? NT : 1];
+    regfft::load_twiddles<R, L, E>(table, p, tw);
+    // component cc of the field on rows ty0 .. ty1-1 of this z into LDS, all
+    // loads first (addresses clamped into ob)
+    const int ty0 = max(ob.y0, ybase - 2), ty1 = min(ob.y1, ybase + 4), nx = ob.nx();
+    const R *plane = o.Hs + cc * o.nob + (long long)zrel * ob.ny() * nx;
+    R hv[TR * E];
+#pragma unroll
+    for (int it = 0; it < TR * E; ++it) {
+        const int e = p + P * it;
+        const int row = e / L, col = e % L;
+        hv[it] = plane[(long long)(min(ty0 + row, ty1 - 1) - ob.y0) * nx + min(col, nx - 1)];
+    }
+#pragma unroll
+    for (int it = 0; it < TR * E; ++it) tile[p + P * it] = hv[it];
+    __syncthreads();
+    auto H = [&](int x, int y) -> double {
+        const int row = min(max(y, ty0), ty1 - 1) - ty0;
+        return (double)tile[row * L + min(max(x - ob.x0, 0), nx - 1)];
+    };
+    cplx<R> v[E];
+    double jsum = 0.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int x = p + P * m;
+        double ja = 0.0, jb = 0.0, ga = 0.0, gb = 0.0;
+        if (x >= ob.x0 && x < ob.x1) {
+            ga = objective_cell(o, cc, x, ybase, z, H, ja);
+            if (two) gb = objective_cell(o, cc, x, ybase + 1, z, H, jb);
+        }
+        jsum += ja;
+        jsum += jb;
+        v[m] = cplx<R>{(R)ga, (R)gb};
+    }
+    // the block's J terms, in a fixed order
+    red[p] = jsum;
+    __syncthreads();
+    for (int w = P / 2; w > 0; w >>= 1) {
+        if (p < w) red[p] += red[p + w];
+        __syncthreads();
+    }
+    regfft::fft_line<R, L, E, true>(v, tw, lds, p, false);
+#pragma unroll
+    for (int m = 0; m < E; ++m) lds[regfft::swz(p + P * m)] = v[m];
+    __syncthreads();
+    // split the pair: row y from the even part, row y + 1 from the odd part
+    const int nys = ob.ny(), nzs = ob.nz();
+    const long long kxs = (long long)nzs * nys;
+    cplx<R> *dst = out + (long long)cc * hx * kxs + (long long)zrel * nys + (ybase - ob.y0);
+    const R half = (R)0.5;
+    for (int e = p; e < 2 * hx; e += P) {
+        const int k = e >> 1, r = e & 1;
+        if (r == 1 && !two) continue;
+        const cplx<R> Zk = lds[regfft::swz(k)];
+        const cplx<R> Zm = lds[regfft::swz((L - k) & (L - 1))];
+        dst[k * kxs + r] = r == 0 ? cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half}
+                                  : cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
+    }
+    // J: the last block to finish adds the block sums in block order
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (p == 0) {
+        o.partials[bid] = red[0];
+        __threadfence();
+        last = atomicAdd(o.ticket, 1u) == (unsigned int)(nb - 1);
+    }
+    __syncthreads();
+    if (last) {
+        // the block sums into LDS by all threads at once, then added in block order
+        __shared__ double sums[kObjMaxBlocks];
+        __threadfence();
+        for (int b = p; b < nb; b += P) sums[b] = o.partials[b];
+        __syncthreads();
+        if (p == 0) {
+            double total = 0.0;
+            for (int b = 0; b < nb; ++b) total += sums[b];
+            *o.J = o.kind == 4 ? -0.5 * o.vcell * total : total / (double)o.S;
+            *o.ticket = 0u;
+        }
     }
 }
 
@@ -681,7 +850,7 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
         const int n = p + P * m;
         if (!(live && n >= p_in && n < p_in + n_in)) v[m] = cplx<R>{0, 0};
     }
-    regfft::fft_line<R, L, E>(v, tw, lds + l * PITCH, p, inv != 0);
+    regfft::fft_line<R, L, E, true>(v, tw, lds + l * PITCH, p, inv != 0);
     if (live) {
         const long long ob = (long long)(line / inner) * out_outer + (long long)(line % inner) * out_inner;
 #pragma unroll
@@ -1055,7 +1224,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, Desi
             }
         }
         cplx<R> *my = lds + l * PITCH;
-        regfft::fft_line<R, L, E>(v, tw, my, p, false);
+        regfft::fft_line<R, L, E, true>(v, tw, my, p, false);
         // natural-order spectrum of the line into LDS (its own slot)
 #pragma unroll
         for (int m = 0; m < E; ++m) my[regfft::swz(p + P * m)] = v[m];
@@ -1090,8 +1259,20 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, Desi
 template <typename R, int L, int E, int NLC, int LPT, int CO>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
                                                                 View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
-                                                                R m0u2, R *grad, const cplx<R> *table)
+                                                                R m0u2, R *grad, const cplx<R> *table, int zrows)
 {
+    if ((int)blockIdx.y >= T.nz()) {
+        // blocks past the target rows zero the gradient rows outside the design
+        // box (T is the design box then); the whole block leaves here
+        const int q0 = ((blockIdx.y - T.nz()) * gridDim.x + blockIdx.x) * kZeroRowsPerBlock;
+        for (int j = 0; j < kZeroRowsPerBlock && q0 + j < zrows; ++j) {
+            int y, z;
+            outside_row(q0 + j, dsg.ny, dsg.design, y, z);
+            R *row = grad + ((long long)z * dsg.ny + y) * dsg.nx;
+            for (int x = threadIdx.x; x < dsg.nx; x += blockDim.x) row[x] = (R)0;
+        }
+        return;
+    }
     constexpr int P = L / E;
     constexpr int TY = 2 * NLC;
     constexpr int PITCH = regfft::padded_len(L);
@@ -1163,7 +1344,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> 
 #pragma unroll
         for (int j = 0; j < LPT; ++j) {
             const int l = l0 + j * (NLC / LPT);
-            regfft::fft_line<R, L, E>(v[j], tw, lds + l * PITCH, p, true);
+            regfft::fft_line<R, L, E, true>(v[j], tw, lds + l * PITCH, p, true);
         }
         __syncthreads();   // the next component restages into the same LDS
 #pragma unroll
@@ -1446,19 +1627,22 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
 
 template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T, const FftPlanDev &plan,
-                         bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad)
+                         bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad, int zrows)
 {
     constexpr int E = 8;
     if ((long long)((T.ny() + 2 * NLC - 1) / (2 * NLC)) * T.nz() < 512 && NLC > 1)
-        return launch_xi_reg<R, L, 1, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-    dim3 grid((T.ny() + 2 * NLC - 1) / (2 * NLC), T.nz());
+        return launch_xi_reg<R, L, 1, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
+    const int gx = (T.ny() + 2 * NLC - 1) / (2 * NLC);
+    // extra block rows for the zero fill, kZeroRowsPerBlock rows each
+    const int gz = (int)((zrows + (long long)gx * kZeroRowsPerBlock - 1) / ((long long)gx * kZeroRowsPerBlock));
+    dim3 grid(gx, T.nz() + gz);
     dim3 block((NLC / LPT) * (L / E));
     if (c == 1)
         TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, 1>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
-                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
+                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows);
     else if (c == 3)
         TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, 3>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
-                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw);
+                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1467,19 +1651,23 @@ hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
 template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
-                            const DesignDev<R> &dsg, const R *m0u, R *grad)
+                            const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside)
 {
+    const long long zr = grad_epilogue && zero_outside ? outside_rows(dsg.ny, dsg.nz, dsg.design) : 0;
+    if (zr > (1LL << 30)) return hipErrorInvalidValue;
+    const int zrows = (int)zr;
     if (c == 1 || c == 3) {
         switch (plan.L) {
-        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
-        case 128: return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad);
+        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
+        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
+        case 128:
+            return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
         case 256:
             return launch_xi_reg<R, 256, TOF_X_NLC256, TOF_X_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
-                                                                    grad);
+                                                                    grad, zrows);
         case 512:
             return launch_xi_reg<R, 512, TOF_X_NLC512, TOF_X_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
-                                                                    grad);
+                                                                    grad, zrows);
         default: break;
         }
     }
@@ -1493,16 +1681,35 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
     dim3 grid((T.ny() + TY - 1) / TY, T.nz());
     TOF_LAUNCH(k_x_inverse<R>, grid, dim3(kThreads), lds, st, C, hx, c, T, plan,
                        grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad, TY, pitch);
+    e = hipGetLastError();
+    if (e != hipSuccess || zrows == 0) return e;
+    TOF_LAUNCH(k_zero_outside<R>, dim3(zrows), dim3(kThreads), 0, st, grad, dsg.nx, dsg.ny, dsg.nz, dsg.design);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_zero_outside(hipStream_t st, R *a, int nx, int ny, int nz, Box keep)
+hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
+                              bool check_only)
 {
-    const int rows = (nz - keep.nz()) * ny + keep.nz() * (ny - keep.ny());
-    if (rows <= 0) return hipSuccess;
-    TOF_LAUNCH(k_zero_outside<R>, dim3(rows), dim3(kThreads), 0, st, a, nx, ny, nz, keep);
-    return hipGetLastError();
+    const long long nb = (long long)((o.ob.ny() + 1) / 2) * o.ob.nz() * o.c_j;
+    if (nb < 1 || nb > kObjMaxBlocks || o.ob.nz() > 65535) return hipErrorInvalidValue;
+    constexpr int E = 8;
+    const dim3 grid((o.ob.ny() + 1) / 2, o.ob.nz(), o.c_j);
+    const cplx<R> *tw = (const cplx<R> *)plan.tw;
+#define TOF_OBJ_CASE(LL)                                                                     \
+    case LL:                                                                                 \
+        if (check_only) return hipSuccess;                                                   \
+        TOF_LAUNCH((k_objective_xf<R, LL, E>), grid, dim3(LL / E), 0, st, o, A, hx, tw);     \
+        return hipGetLastError();
+    switch (plan.L) {
+        TOF_OBJ_CASE(32)
+        TOF_OBJ_CASE(64)
+        TOF_OBJ_CASE(128)
+        TOF_OBJ_CASE(256)
+        TOF_OBJ_CASE(512)
+    default: return hipErrorInvalidValue;
+    }
+#undef TOF_OBJ_CASE
 }
 
 template <typename R>
@@ -1638,8 +1845,9 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                          const FftPlanDev &, BlockMap);                                  \
     template hipError_t launch_x_inverse<R>(hipStream_t, const cplx<R> *, int, int, Box,                 \
                                             const FftPlanDev &, bool, View4<R>, const DesignDev<R> &,    \
-                                            const R *, R *);                                             \
-    template hipError_t launch_zero_outside<R>(hipStream_t, R *, int, int, int, Box);                    \
+                                            const R *, R *, bool);                                       \
+    template hipError_t launch_objective_xf<R>(hipStream_t, const ObjectiveDev<R> &, const FftPlanDev &,  \
+                                               cplx<R> *, int, bool);                                     \
     template hipError_t launch_objective<R>(hipStream_t, int, const R *, Box, Box, int, double, double,  \
                                             double, double, double, const double *, double *, R *,       \
                                             double *, unsigned int *);                                   \

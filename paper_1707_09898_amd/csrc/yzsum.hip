@@ -8,7 +8,10 @@
 //   gather  (few target rows): per kx, the y FFT of every source row times
 //           Kt, summed over the source rows of a group; each group's sum is
 //           a partial spectrum row, and the inverse y pass adds the partials
-//           (in group order) before transforming.
+//           (in group order) before transforming.  (Adding them in the last
+//           block of each kx instead needs a device-scope release per block,
+//           an L2 write-back on this chip, which costs far more than the
+//           separate pass.)
 //   scatter (few source rows): per kx, the y FFT of the source rows (kept in
 //           LDS), then for every target row the sum against Kt and the
 //           inverse y FFT, written straight into the layout of the inverse x
@@ -42,6 +45,41 @@ __device__ __forceinline__ void load_line(const cplx<R> *row, int y0, int ny, in
         const cplx<R> a = row[min(max(n - y0, 0), ny - 1)];
         v[m] = (ok && n >= y0 && n < y0 + ny) ? a : cplx<R>{0, 0};
     }
+}
+
+// Kt_q(kx, ky, d) at a line thread's frequencies ky = p + P m, m < E.  Only
+// the half ky <= L/2 is read (L/2 + 1 values a line): the other half follows
+// from the parity in y of each component (Kt(L - ky) = Kt(ky), negated for
+// xy and yz, which are odd in y), taken from lane P - p of the same line,
+// slot E - 1 - m (lane 0 keeps its own slot E - m).
+template <typename R, int L, int E, int NC>
+__device__ __forceinline__ void kt_line(const KtDev<R> &kt, const ProductDev &prod, int kx, int p, int d,
+                                        R (*K)[NC])
+{
+    constexpr int P = L / E;
+    constexpr int H = E / 2;
+    static_assert(E % 2 == 0 && 64 % P == 0, "a line spans a power-of-two lane group");
+    R lo[H + 1][NC];
+#pragma unroll
+    for (int m = 0; m < H; ++m) kt_at<R, NC>(kt, prod, kx, p + P * m, d, lo[m]);
+    kt_at<R, NC>(kt, prod, kx, L / 2, d, lo[H]);   // ky = L/2: lane 0's slot H
+    const int lane = threadIdx.x & 63;
+    const int src = lane - p + ((P - p) & (P - 1));
+#pragma unroll
+    for (int m = 0; m < H; ++m)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) K[m][q] = lo[m][q];
+#pragma unroll
+    for (int m = H; m < E; ++m)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int c = NC == 6 ? q : prod.comp[q];
+            const unsigned oy = (c == 3 || c == 5) ? kSignBit : 0u;
+            const R mirrored = flip_sign(__shfl(lo[E - 1 - m][q], src), oy);
+            // lane 0: ky = P m mirrors to P (E - m), its own slot (m = H is ky = L/2 itself,
+            // where the odd components vanish, so no sign is needed)
+            K[m][q] = p == 0 ? (m == H ? lo[H][q] : flip_sign(lo[E - m][q], oy)) : mirrored;
+        }
 }
 
 // Few target rows.  Block (kx, g) takes source rows [g rpg, (g+1) rpg) of
@@ -79,18 +117,16 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int h
         const int zrc = min(zr, rb - 1);
         // tensor values (independent of the transform) and the lines, all loads first;
         // a row past the range transforms zeros
-        R K[E][NR][NC];
+        R K[NR][E][NC];
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                kt_at<R, NC>(kt, prod, kx, p + P * m, zt0 + min(r, nzt - 1) - (zs0 + zrc), K[m][r]);
+        for (int r = 0; r < NR; ++r)
+            kt_line<R, L, E, NC>(kt, prod, kx, p, zt0 + min(r, nzt - 1) - (zs0 + zrc), K[r]);
         cplx<R> X[CI][E];
 #pragma unroll
         for (int i = 0; i < CI; ++i)
             load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + zrc) * nys, ys0, nys, p, ok, X[i]);
 #pragma unroll
-        for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E>(X[i], tw, my, p, false);
+        for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E, true>(X[i], tw, my, p, false);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             cplx<R> xm[CI];
@@ -98,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int h
             for (int i = 0; i < CI; ++i) xm[i] = X[i][m];
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                if (r < nzt) zsum_mac<R, CI, CO, NC>(prod, K[m][r], xm, acc[r][m]);
+                if (r < nzt) zsum_mac<R, CI, CO, NC>(prod, K[r][m], xm, acc[r][m]);
         }
     }
     // the slots' sums, added in slot order
@@ -152,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_scatter(const cplx<R> *A, int 
         const int r = qc / CI, i = qc % CI;
         cplx<R> v[E];
         load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + r) * nys, ys0, nys, p, ok, v);
-        regfft::fft_line<R, L, E>(v, tw, my, p, false);
+        regfft::fft_line<R, L, E, true>(v, tw, my, p, false);
         if (ok) {
 #pragma unroll
             for (int m = 0; m < E; ++m) xs[q * L + p + P * m] = v[m];
@@ -165,12 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_scatter(const cplx<R> *A, int 
         const int zr = ra + it * NL + l;
         const bool ok = zr < rb;
         const int zrc = min(zr, rb - 1);
-        R K[E][NR][NC];
+        R K[NR][E][NC];
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                kt_at<R, NC>(kt, prod, kx, p + P * m, zt0 + zrc - (zs0 + min(r, nzs - 1)), K[m][r]);
+        for (int r = 0; r < NR; ++r)
+            kt_line<R, L, E, NC>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), K[r]);
         cplx<R> Y[CO][E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -183,14 +217,14 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_scatter(const cplx<R> *A, int 
                 cplx<R> xm[CI];
 #pragma unroll
                 for (int i = 0; i < CI; ++i) xm[i] = xs[(r * CI + i) * L + p + P * m];
-                zsum_mac<R, CI, CO, NC>(prod, K[m][r], xm, out);
+                zsum_mac<R, CI, CO, NC>(prod, K[r][m], xm, out);
             }
 #pragma unroll
             for (int o = 0; o < CO; ++o) Y[o][m] = out[o];
         }
 #pragma unroll
         for (int o = 0; o < CO; ++o) {
-            regfft::fft_line<R, L, E>(Y[o], tw, my, p, true);
+            regfft::fft_line<R, L, E, true>(Y[o], tw, my, p, true);
             if (ok) {
                 cplx<R> *dst = C + (((long long)o * hx + kx) * nzt + zrc) * nyt - yt0;
 #pragma unroll
@@ -229,14 +263,14 @@ hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                                   a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
+                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
                 return hipGetLastError();
             }
         } else {
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                                   a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
+                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
                 return hipGetLastError();
             }
         }

@@ -25,11 +25,11 @@ EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "
            "tof_padded_lengths", "tof_workspace_bytes", "tof_last_error", "tof_dd_newell_host",
            "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option"]
 
-OPT_ZSUM, OPT_FUSE_YZ = 1, 2
+OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE = 1, 2, 3
 
 PROFILE_SLOTS = 12
 PROFILE_NAMES = ["fwd_x", "fwd_y", "fwd_z_product", "fwd_inv_y", "fwd_inv_x_field", "objective",
-                 "adj_x", "adj_y", "adj_z_product", "adj_inv_y", "adj_inv_x_grad", "zero_fill"]
+                 "adj_x", "adj_y", "adj_z_product", "adj_inv_y", "adj_inv_x_grad", "reserved"]
 
 
 class TofError(RuntimeError):
@@ -226,7 +226,7 @@ class Engine:
         return [lib().tof_profile_kernel(self._ctx, i).decode() for i in range(PROFILE_SLOTS)]
 
     def set_option(self, option: int, value: bool):
-        """Pass choice (OPT_ZSUM, OPT_FUSE_YZ); see tof_set_option."""
+        """Pass choice (OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE); see tof_set_option."""
         self._check(lib().tof_set_option(self._ctx, int(option), 1 if value else 0))
 
     def padded_lengths(self) -> Tuple[int, int, int]:

@@ -49,17 +49,20 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-# pass choices: y transforms fused with the direct z sum, the direct z sum
-# alone, FFTs along z (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ)
-PATHS = {"fused": (1, 1), "zsum": (1, 0), "zfft": (0, 0)}
+# pass choices: the fused kernels (y transforms with the direct z sum, the
+# objective with the adjoint's x pass), the direct z sum in its own pass with
+# the objective in its own kernel, FFTs along z
+# (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ, TOF_OPT_FUSE_OBJECTIVE)
+PATHS = {"fused": (1, 1, 1), "zsum": (1, 0, 0), "zfft": (0, 0, 0)}
 
 
 def engine_on_path(w, dtype, path):
     t = tof()
     e = t.engine_for(w, dtype)
-    zsum, fuse = PATHS[path]
+    zsum, fuse, fobj = PATHS[path]
     e.set_option(t.OPT_ZSUM, zsum)
     e.set_option(t.OPT_FUSE_YZ, fuse)
+    e.set_option(t.OPT_FUSE_OBJECTIVE, fobj)
     return e
 
 
@@ -178,6 +181,8 @@ def test_gpu_is_deterministic_and_stream_safe(torch):
     rho = dev(torch, w.rho, torch.float32)
     J1, g1 = e.objective_and_grad(rho)
     s = torch.cuda.Stream()
+    # calls on one context must not overlap: the side stream waits for the first call
+    s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         J2, g2 = e.objective_and_grad(rho)
     s.synchronize()
