@@ -34,6 +34,39 @@ using namespace tofdev;
 constexpr int kThreads = 256;
 
 
+// x[m] <- x[m]^p, m < N, by repeated multiplication from the left (the same
+// rounding as ipow_dev); p is uniform, so one branch serves all N values.
+template <typename R, int N>
+__device__ __forceinline__ void ipow_n(R *x, int p)
+{
+    switch (p) {
+    case 0:
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] = (R)1;
+        break;
+    case 1: break;
+    case 2:
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] = x[m] * x[m];
+        break;
+    case 3:
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] = x[m] * x[m] * x[m];
+        break;
+    case 4:
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] = x[m] * x[m] * x[m] * x[m];
+        break;
+    default:
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            R v = x[m];
+            for (int i = 1; i < p; ++i) v *= x[m];
+            x[m] = v;
+        }
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ R ipow_dev(R x, int p)
 {
@@ -1214,12 +1247,14 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, Desi
                     if (!dsg.mask[offB + xc]) fb[m] = 0;
                 }
             }
+            ipow_n<R, E>(ra, dsg.p);
+            ipow_n<R, E>(rb, dsg.p);
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const int x = p + P * m;
                 const bool in = x >= xl && x < xh;
-                const R a = (in && inA) ? ipow_dev(ra[m], dsg.p) * fa[m] : (R)0;
-                const R b = (in && inB) ? ipow_dev(rb[m], dsg.p) * fb[m] : (R)0;
+                const R a = (in && inA) ? ra[m] * fa[m] : (R)0;
+                const R b = (in && inB) ? rb[m] * fb[m] : (R)0;
                 v[m] = cplx<R>{a, b};
             }
         }
@@ -1235,21 +1270,25 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, Desi
     const long long kxs = (long long)nzs * nys;
     cplx<R> *o = out + (long long)c * hx * kxs + (long long)zrel * nys + (ybase - S.y0);
     const R half = (R)0.5;
+    // thread: one row r, frequencies k0, k0 + KSTEP, ...
     constexpr int NTH = (NLC / LPT) * P;
-    constexpr int NIT = ((L / 2 + 1) * TY + NTH - 1) / NTH;
+    constexpr int KSTEP = NTH / TY;
+    constexpr int NIT = (L / 2 + 1 + KSTEP - 1) / KSTEP;
+    static_assert(NTH % TY == 0, "whole rows per sweep");
+    const int r = threadIdx.x % TY, k0 = threadIdx.x / TY;
+    if (r >= nrow) return;
+    const cplx<R> *line = lds + (r >> 1) * PITCH;
+    const bool odd = r & 1;
+    cplx<R> *op = o + (long long)k0 * kxs + r;
+    const long long ostep = (long long)KSTEP * kxs;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int e = threadIdx.x + it * NTH;
-        const int k = e / TY;
-        const int r = e % TY;
-        if (k >= hx || r >= nrow) continue;
-        const cplx<R> *line = lds + (r >> 1) * PITCH;
+        const int k = k0 + it * KSTEP;
+        if (k >= hx) break;
         const cplx<R> Zk = line[regfft::swz(k)];
         const cplx<R> Zm = line[regfft::swz((L - k) & (L - 1))];
-        cplx<R> w;
-        if ((r & 1) == 0) w = cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half};
-        else w = cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
-        o[k * kxs + r] = w;
+        op[it * ostep] = odd ? cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half}
+                             : cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half};
     }
 }
 
@@ -1300,22 +1339,26 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> 
     for (int cc = 0; cc < CO; ++cc) {
         // stage the half spectra of the TY rows as [r][k]: all loads first
         // (a batch of registers), then the LDS stores
+        // thread: one row r, frequencies k0, k0 + KSTEP, ...
         constexpr int NTH = (NLC / LPT) * P;
-        constexpr int NIT = (HX * TY + NTH - 1) / NTH;
+        constexpr int KSTEP = NTH / TY;
+        constexpr int NIT = (HX + KSTEP - 1) / KSTEP;
+        static_assert(NTH % TY == 0, "whole rows per sweep");
+        const int r = threadIdx.x % TY, k0 = threadIdx.x / TY;
+        const cplx<R> *src = C + ((long long)(cc * hx + k0) * nzt + zrel) * nyt + (ybase - T.y0 + min(r, nrow - 1));
+        const long long sstep = (long long)KSTEP * nzt * nyt;
         cplx<R> stg[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int e = threadIdx.x + it * NTH;
-            const int r = e % TY;
-            const int k = e / TY;
-            stg[it] = (e < HX * TY && r < nrow)
-                          ? C[((long long)(cc * hx + k) * nzt + zrel) * nyt + (ybase - T.y0 + r)]
-                          : cplx<R>{0, 0};
+            const int k = k0 + it * KSTEP;
+            // rows past nrow and frequencies past hx read a clamped address
+            const cplx<R> a = src[min(it, (hx - 1 - k0) / KSTEP) * sstep];
+            stg[it] = (k < HX && r < nrow) ? a : cplx<R>{0, 0};
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int e = threadIdx.x + it * NTH;
-            if (e < HX * TY) lds[(e % TY) * HX + e / TY] = stg[it];
+            const int k = k0 + it * KSTEP;
+            if (k < HX) lds[r * HX + k] = stg[it];
         }
         __syncthreads();
         cplx<R> v[LPT][E];
@@ -1411,13 +1454,13 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> 
 #pragma unroll
                     for (int m = 0; m < E; ++m) mk[m] = dsg.mask[off + min(p + P * m, dsg.nx - 1)] != 0;
                 }
+                ipow_n<R, E>(rv, dsg.p - 1);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int x = p + P * m;
                     if (x >= dsg.nx) continue;
                     R g = 0;
-                    if (rowin && x >= xl && x < xh && mk[m])
-                        g = (R)dsg.p * ipow_dev(rv[m], dsg.p - 1) * acc[j][h][m];
+                    if (rowin && x >= xl && x < xh && mk[m]) g = (R)dsg.p * rv[m] * acc[j][h][m];
                     gr[x] = g;
                 }
             }
