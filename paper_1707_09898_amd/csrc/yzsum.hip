@@ -52,17 +52,27 @@ __device__ __forceinline__ void load_line(const cplx<R> *row, int y0, int ny, in
 // from the parity in y of each component (Kt(L - ky) = Kt(ky), negated for
 // xy and yz, which are odd in y), taken from lane P - p of the same line,
 // slot E - 1 - m (lane 0 keeps its own slot E - m).
+//
+// kt_half loads the half (slots 0 .. E/2 - 1 and ky = L/2); kt_full completes
+// the line, so the loads of a later row can be issued before the lane
+// exchange of the current one.
 template <typename R, int L, int E, int NC>
-__device__ __forceinline__ void kt_line(const KtDev<R> &kt, const ProductDev &prod, int kx, int p, int d,
-                                        R (*K)[NC])
+__device__ __forceinline__ void kt_half(const KtDev<R> &kt, const ProductDev &prod, int kx, int p, int d,
+                                        R (*lo)[NC])
+{
+    constexpr int P = L / E;
+    constexpr int H = E / 2;
+#pragma unroll
+    for (int m = 0; m < H; ++m) kt_at<R, NC>(kt, prod, kx, p + P * m, d, lo[m]);
+    kt_at<R, NC>(kt, prod, kx, L / 2, d, lo[H]);   // ky = L/2: lane 0's slot H
+}
+
+template <typename R, int L, int E, int NC>
+__device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (*lo)[NC], R (*K)[NC])
 {
     constexpr int P = L / E;
     constexpr int H = E / 2;
     static_assert(E % 2 == 0 && 64 % P == 0, "a line spans a power-of-two lane group");
-    R lo[H + 1][NC];
-#pragma unroll
-    for (int m = 0; m < H; ++m) kt_at<R, NC>(kt, prod, kx, p + P * m, d, lo[m]);
-    kt_at<R, NC>(kt, prod, kx, L / 2, d, lo[H]);   // ky = L/2: lane 0's slot H
     const int lane = threadIdx.x & 63;
     const int src = lane - p + ((P - p) & (P - 1));
 #pragma unroll
@@ -109,22 +119,25 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int h
         for (int m = 0; m < E; ++m)
 #pragma unroll
             for (int o = 0; o < CO; ++o) acc[r][m][o] = cplx<R>{0, 0};
-    // the same trip count in every slot: the transforms hold block barriers
+    // the same trip count in every slot (a row past the range transforms zeros)
     const int nit = (rb - ra + NL - 1) / NL;
+    constexpr int H = E / 2;
     for (int it = 0; it < nit; ++it) {
         const int zr = ra + it * NL + l;
-        const bool ok = zr < rb;
         const int zrc = min(zr, rb - 1);
-        // tensor values (independent of the transform) and the lines, all loads first;
-        // a row past the range transforms zeros
-        R K[NR][E][NC];
+        // tensor values (independent of the transform) and the lines, all loads first
+        // (fetching the next row ahead instead raises the register count and gains nothing)
+        R Kh[NR][H + 1][NC];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            kt_line<R, L, E, NC>(kt, prod, kx, p, zt0 + min(r, nzt - 1) - (zs0 + zrc), K[r]);
+            kt_half<R, L, E, NC>(kt, prod, kx, p, zt0 + min(r, nzt - 1) - (zs0 + zrc), Kh[r]);
         cplx<R> X[CI][E];
 #pragma unroll
         for (int i = 0; i < CI; ++i)
-            load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + zrc) * nys, ys0, nys, p, ok, X[i]);
+            load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + zrc) * nys, ys0, nys, p, zr < rb, X[i]);
+        R K[NR][E][NC];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC>(prod, p, Kh[r], K[r]);
 #pragma unroll
         for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E, true>(X[i], tw, my, p, false);
 #pragma unroll
@@ -197,14 +210,24 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_scatter(const cplx<R> *A, int 
     __syncthreads();
     const int ra = blockIdx.y * rpg, rb = min(ra + rpg, nzt);
     const int nit = (rb - ra + NL - 1) / NL;
+    constexpr int H = E / 2;
+    // the tensor values of iteration `it`, loaded one iteration ahead
+    R Kh[NR][H + 1][NC];
+    auto fetch = [&](int it, R (*Kf)[H + 1][NC]) {
+        const int zrc = min(ra + it * NL + l, rb - 1);
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            kt_half<R, L, E, NC>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), Kf[r]);
+    };
+    fetch(0, Kh);
     for (int it = 0; it < nit; ++it) {
         const int zr = ra + it * NL + l;
         const bool ok = zr < rb;
         const int zrc = min(zr, rb - 1);
         R K[NR][E][NC];
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            kt_line<R, L, E, NC>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), K[r]);
+        for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC>(prod, p, Kh[r], K[r]);
+        fetch(it + 1, Kh);   // unconditional, see the gather
         cplx<R> Y[CO][E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
