@@ -72,6 +72,52 @@ def cpu_baseline(w, layers=16):
                       f"{z1 - z0} design layers scaled linearly; FP64; {t2 - t0:.1f} s measured"}
 
 
+def batch_measurement(torch, wl, args):
+    """64 independent designs of uneven size (FP32), padded lengths chosen by
+    the autotuner, one graph replay per batch evaluation."""
+    from paper_1707_09898_amd import autotune
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = wl.config5()
+    t0 = time.perf_counter()
+    lengths = None
+    if not args.no_autotune:
+        lengths = [autotune.tune(w, "f32", evals=2)[0] for w in ws]
+    t1 = time.perf_counter()
+    b = DesignBatch(ws, "f32", lengths, streams=args.batch_streams)
+    nbytes = b.algorithmic_bytes()
+    b.capture()
+    for _ in range(3):
+        b.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.batch_replays):
+        b.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batch_replays
+    # eager launches of the same batch, for comparison
+    b.run_eager()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        b.run_eager()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / 5
+    cells = int(sum(int(w.n[0]) * int(w.n[1]) * int(w.n[2]) for w in ws))
+    res = {"designs": len(ws), "cells": cells, "ms_per_batch": ms, "evals_per_s": len(ws) * 1000.0 / ms,
+           "ms_per_batch_eager": ms_eager, "bytes_per_batch": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
+           "streams": args.batch_streams, "autotuned": not args.no_autotune,
+           "autotune_s": round(t1 - t0, 1),
+           "lengths": [list(map(int, e.padded_lengths())) for e in b.engines]}
+    b.close()
+    print(f"[bench] c5 batch: {ms:.3f} ms per 64 designs ({res['evals_per_s']:.0f} evals/s), eager {ms_eager:.3f} ms",
+          file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +126,10 @@ def main():
     ap.add_argument("--f64-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch measurement")
+    ap.add_argument("--batch-replays", type=int, default=20)
+    ap.add_argument("--batch-streams", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true", help="batch with the default padded lengths")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB three times (a known-size kernel for "
                          "calibrating memory counters)")
@@ -165,6 +215,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": dom[3], "avg_launch_us": dom[1] * 1e3},
     }
+    if not args.no_batch:
+        out["c5_batch"] = batch_measurement(torch, wl, args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

@@ -238,10 +238,11 @@ class Engine:
         return int(lib().tof_workspace_bytes(self._ctx))
 
 
-def engine_for(w, dtype: str = "f32", stream=None) -> Engine:
-    """An Engine set up for a workload description (workloads.Workload)."""
+def engine_for(w, dtype: str = "f32", stream=None, L=None) -> Engine:
+    """An Engine set up for a workload description (workloads.Workload); L
+    overrides the workload's padded lengths."""
     import torch
-    e = Engine(w.n, w.h, dtype, L=w.pad, stream=stream)
+    e = Engine(w.n, w.h, dtype, L=w.pad if L is None else L, stream=stream)
     tdt = e.dtype
     m0f = None
     if w.m0_field is not None:

@@ -1,0 +1,132 @@
+"""The batching form: independent designs of uneven size run as one HIP graph
+(graph replays against eager launches and against the oracle), and the
+padded-length autotuner (its candidate rule on the CPU; tuned lengths give
+the same result on the GPU)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_09898_amd import autotune
+from paper_1707_09898_amd import workloads as wl
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def smallest_designs(count):
+    ws = wl.config5()
+    order = sorted(range(len(ws)), key=lambda i: int(np.prod(ws[i].n)))
+    return [ws[i] for i in order[:count]]
+
+
+# ---------------------------------------------------------------- CPU
+def brute_smooth7(L):
+    return L >= 1 and all(p in (2, 3, 5, 7) for p in prime_factors(L))
+
+
+def prime_factors(L):
+    out, d = [], 2
+    while d * d <= L:
+        while L % d == 0:
+            out.append(d)
+            L //= d
+        d += 1
+    if L > 1:
+        out.append(L)
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 16, 33, 37, 64, 97, 101, 160, 257, 512])
+def test_candidate_lengths_are_valid(n):
+    cands = autotune.candidate_lengths(n)
+    assert cands[0] == min(L for L in range(2 * n, 4 * n + 8, 2) if brute_smooth7(L))
+    for L in cands:
+        assert L % 2 == 0 and L >= 2 * n - 1 and L <= autotune.MAX_L and brute_smooth7(L)
+    if len(cands) > 1:
+        assert cands[1] & (cands[1] - 1) == 0
+
+
+def test_candidate_triples_start_with_the_default():
+    t = autotune.candidate_triples((37, 64, 33))
+    assert t[0] == (80, 128, 70) and (128, 128, 128) in t and len(set(t)) == len(t)
+
+
+# ---------------------------------------------------------------- GPU
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.mark.gpu
+def test_graph_replays_match_eager_launches(torch):
+    """Six designs of the 64-design batch on three streams: every replay of
+    the captured graph reproduces the eager results bit for bit, with other
+    device work and synchronizations between the replays."""
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = smallest_designs(6)
+    say("batch graph", [w.n for w in ws])
+    b = DesignBatch(ws, "f32", streams=3)
+    b.run_eager()
+    ref = b.results()
+    b.capture()
+    for k in range(3):
+        for g in b.grad:
+            g.fill_(float("nan"))
+        for J in b.J:
+            J.fill_(float("nan"))
+        torch.cuda.synchronize()
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()   # the program's own eager work between replays
+        b.replay()
+        got = b.results()
+        for (J0, g0), (J1, g1) in zip(ref, got):
+            assert J0 == J1 and np.array_equal(g0, g1), k
+    b.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_batch_matches_oracle(torch, dtype, tol):
+    """The two smallest designs of the batch, evaluated by a graph replay,
+    against the oracle's J and full gradient."""
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = smallest_designs(2)
+    b = DesignBatch(ws, dtype, streams=2)
+    b.capture()
+    b.replay()
+    got = b.results()
+    b.close()
+    for w, (J, g) in zip(ws, got):
+        say("batch oracle", dtype, w.n, w.p)
+        Jr, gr, _ = oracle.objective_and_grad(w)
+        assert abs(J - Jr) <= tol * abs(Jr)
+        assert np.abs(g.astype(np.float64) - gr).max() <= tol * np.abs(gr).max()
+
+
+@pytest.mark.gpu
+def test_tuned_lengths_give_the_same_result(torch):
+    """Every candidate length triple of a design gives the same J and
+    gradient (FP64, to 1e-12), and the tuner returns one of them."""
+    from paper_1707_09898_amd import tof
+    w = smallest_designs(1)[0]
+    best, times = autotune.tune(w, "f64", evals=2)
+    say("tuned", w.n, best, times)
+    assert best in times and len(times) == len(autotune.candidate_triples(w.n))
+    res = []
+    for L in times:
+        e = tof.engine_for(w, "f64", L=L)
+        assert e.padded_lengths() == tuple(L)
+        J, g = e.objective_and_grad(torch.as_tensor(w.rho, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        res.append((J.item(), g.cpu().numpy()))
+        e.close()
+    J0, g0 = res[0]
+    for J, g in res[1:]:
+        assert abs(J - J0) <= 1e-12 * abs(J0)
+        assert np.abs(g - g0).max() <= 1e-12 * np.abs(g0).max()
