@@ -21,6 +21,8 @@ if ROOT not in sys.path:
 
 METRIC = "gradient evals/s (fwd+adjoint) at 256x256x128 FP32 vs FP64 plain; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 summary of this workload (kernel trace + FETCH_SIZE / WRITE_SIZE runs)
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gradient_eval_256x256x128_kernels.md")
 
 
 def model_bytes_per_eval(w, wsize, L):
@@ -127,6 +129,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch measurement")
+    ap.add_argument("--no-paths", action="store_true", help="skip timing the unfused pass choices")
     ap.add_argument("--batch-replays", type=int, default=20)
     ap.add_argument("--batch-streams", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true", help="batch with the default padded lengths")
@@ -170,9 +173,21 @@ def main():
         for _ in range(args.profile_steps):
             e.objective_and_grad(rho, grad, J)
         prof = e.profile_read()
-        kernels = e.profile_kernels()
+        kernels = e.profile_kernels(with_items=True)
         e.profile(False)
-        results[dtype] = {"ms": ms, "prof": prof, "kernels": kernels, "L": L, "J": float(J.item())}
+        paths = {}
+        if dtype == "f32" and not args.no_paths:
+            # the same evaluation on the other pass choices (direct z sum unfused; FFTs along z)
+            for name, (zs, fu, fo) in (("zsum", (1, 0, 0)), ("zfft", (0, 0, 0))):
+                e.set_option(tof.OPT_ZSUM, zs)
+                e.set_option(tof.OPT_FUSE_YZ, fu)
+                e.set_option(tof.OPT_FUSE_OBJECTIVE, fo)
+                for _ in range(3):
+                    e.objective_and_grad(rho, grad, J)
+                paths[name] = 1000.0 / time_steps(torch, e, rho, grad, J, max(10, steps // 4))
+            for opt in (tof.OPT_ZSUM, tof.OPT_FUSE_YZ, tof.OPT_FUSE_OBJECTIVE):
+                e.set_option(opt, 1)
+        results[dtype] = {"ms": ms, "prof": prof, "kernels": kernels, "L": L, "J": float(J.item()), "paths": paths}
         print(f"[bench] {dtype}: {ms:.4f} ms/eval, {1000.0 / ms:.1f} evals/s, J={J.item():.10e}",
               file=sys.stderr, flush=True)
         e.close()
@@ -184,7 +199,16 @@ def main():
     slots = [(name, ms_tot / cnt, cnt, by) for (name, ms_tot, cnt, by) in r32["prof"] if cnt > 0]
     dom = max(slots, key=lambda s: s[1])
     dom_idx = tof.PROFILE_NAMES.index(dom[0])
+    dom_kernel, dom_items = r32["kernels"][dom_idx]
     achieved = dom[3] / (dom[1] * 1e-3) / 1e9
+    from paper_1707_09898_amd import rocprof_summary
+    traffic, same_src = rocprof_summary.lookup(TRAFFIC_SUMMARY, dom_kernel, "float", dom_items)
+    traffic_note = ("FETCH_SIZE + WRITE_SIZE bytes per launch (copy-calibrated), "
+                    + os.path.relpath(TRAFFIC_SUMMARY, ROOT)) if traffic is not None and same_src else \
+        ("kernel sources changed since the counters were taken" if traffic is not None else
+         "no counter summary for this kernel launch")
+    if not same_src:
+        traffic = None
     pass_bytes = sum(by for (_, _, cnt, by) in slots)
     model = model_bytes_per_eval(w, wsize, r32["L"])
     out = {
@@ -208,11 +232,12 @@ def main():
         "speedup_f32_over_f64": results["f64"]["ms"] / r32["ms"],
         "bytes_per_eval": {"passes": pass_bytes, "full_field_model": model},
         "effective_GBps": {"passes": pass_bytes * evals / 1e9, "full_field_model": model * evals / 1e9},
-        "per_kernel_us": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)]}": round(avg * 1e3, 2)
+        "per_kernel_us": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)][0]}": round(avg * 1e3, 2)
                           for (name, avg, _, _) in slots},
-        "roofline": {"bound": "hbm", "kernel": f"{r32['kernels'][dom_idx]} ({dom[0]})",
+        "paths_f32_evals_per_s": dict({"fused": evals}, **r32["paths"]),
+        "roofline": {"bound": "hbm", "kernel": f"{dom_kernel} ({dom[0]}, {dom_items} work items)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "bytes_per_launch": dom[3], "avg_launch_us": dom[1] * 1e3},
     }
     if not args.no_batch:

@@ -202,9 +202,11 @@ tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[]
 
 /*
  * Name of the kernel last timed in a slot (e.g. "k_yzsum_gather"), "" if
- * none; valid until the next timed call on the context.
+ * none; valid until the next timed call on the context.  *work_items (if not
+ * NULL) receives that launch's grid size times block size (the work-item
+ * count profilers report), 0 if none.
  */
-const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot);
+const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_items);
 
 /*
  * Pass choices, each 0 or 1 (default 1); the result is the same convolution

@@ -15,6 +15,7 @@
 #include "engine.h"
 
 thread_local const char *g_last_kernel = "";
+thread_local long long g_last_items = 0;
 
 namespace {
 
@@ -82,6 +83,7 @@ struct tof_ctx {
     std::vector<hipEvent_t> prof_ev;   // [slot][call][2]
     double prof_bytes[TOF_PROFILE_SLOTS] = {};
     std::string prof_kernel[TOF_PROFILE_SLOTS];
+    long long prof_items[TOF_PROFILE_SLOTS] = {};
     // pass choices (tof_set_option)
     bool opt_zsum = true;    // direct z sum against Kt for few source / target rows
     bool opt_fuse = true;    // that sum fused with the y transforms
@@ -132,6 +134,7 @@ hipError_t timed(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn)
     std::string k = g_last_kernel;
     if (!k.empty() && k[0] == '(') k = k.substr(1);
     ctx->prof_kernel[slot] = k.substr(0, k.find_first_of("<(), "));
+    ctx->prof_items[slot] = g_last_items;
     return hipSuccess;
 }
 
@@ -842,9 +845,11 @@ tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[]
     return TOF_OK;
 }
 
-const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot)
+const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_items)
 {
+    if (work_items) *work_items = 0;
     if (!ctx || slot < 0 || slot >= TOF_PROFILE_SLOTS) return "";
+    if (work_items) *work_items = ctx->prof_items[slot];
     return ctx->prof_kernel[slot].c_str();
 }
 

@@ -111,13 +111,16 @@ struct YzSumArgs {
     int rpg;                 // rows per block group: source rows (gather) or target rows (scatter)
 };
 
-// Text of the kernel expression last launched by this thread (for the
-// per-launch timing record); set by TOF_LAUNCH.
+// Text of the kernel expression last launched by this thread and its work
+// items (grid times block), for the per-launch timing record; set by TOF_LAUNCH.
 extern thread_local const char *g_last_kernel;
-#define TOF_LAUNCH(K, ...)                 \
-    do {                                   \
-        g_last_kernel = #K;                \
-        hipLaunchKernelGGL(K, __VA_ARGS__); \
+extern thread_local long long g_last_items;
+#define TOF_LAUNCH(K, G, B, ...)                                                                  \
+    do {                                                                                          \
+        g_last_kernel = #K;                                                                       \
+        const dim3 g_ = dim3(G), b_ = dim3(B);                                                    \
+        g_last_items = (long long)g_.x * g_.y * g_.z * b_.x * b_.y * b_.z;                        \
+        hipLaunchKernelGGL(K, g_, b_, __VA_ARGS__);                                               \
     } while (0)
 
 // ---- host launchers (kernels.hip); all enqueue on `st` and return hipError_t ----

@@ -85,7 +85,7 @@ def lib():
         L.tof_dd_newell_host.restype = dbl
         L.tof_profile_enable.argtypes = [vp, i32]
         L.tof_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
-        L.tof_profile_kernel.argtypes = [vp, i32]
+        L.tof_profile_kernel.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.tof_profile_kernel.restype = ctypes.c_char_p
         L.tof_set_option.argtypes = [vp, i32, i32]
         for name in ("tof_create", "tof_set_design", "tof_set_objective", "tof_field",
@@ -221,9 +221,15 @@ class Engine:
         self._check(lib().tof_profile_read(self._ctx, ms, cnt, by))
         return [(PROFILE_NAMES[i], ms[i], cnt[i], by[i]) for i in range(PROFILE_SLOTS)]
 
-    def profile_kernels(self):
-        """Per slot: the name of the kernel last timed there ("" if none)."""
-        return [lib().tof_profile_kernel(self._ctx, i).decode() for i in range(PROFILE_SLOTS)]
+    def profile_kernels(self, with_items: bool = False):
+        """Per slot: the name of the kernel last timed there ("" if none), or
+        (name, work items of that launch) with with_items."""
+        out = []
+        for i in range(PROFILE_SLOTS):
+            n = ctypes.c_int64(0)
+            name = lib().tof_profile_kernel(self._ctx, i, ctypes.byref(n)).decode()
+            out.append((name, int(n.value)) if with_items else name)
+        return out
 
     def set_option(self, option: int, value: bool):
         """Pass choice (OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE); see tof_set_option."""

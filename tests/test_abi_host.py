@@ -63,7 +63,7 @@ def test_null_context_calls_fail_cleanly():
     assert L.tof_tensor(None, None, None) == -1
     assert L.tof_workspace_bytes(None) == 0
     assert L.tof_set_option(None, tof.OPT_FUSE_YZ, 1) == -1
-    assert L.tof_profile_kernel(None, 0) == b""
+    assert L.tof_profile_kernel(None, 0, None) == b""
     L.tof_destroy(None)
 
 
