@@ -182,10 +182,11 @@ tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream);
  * inverse y, inverse x with its epilogue), 5 the objective (with
  * TOF_OPT_FUSE_OBJECTIVE also the adjoint's x pass, slot 6 then unused), 6-10
  * the passes of the adjoint convolution (the last one also zeroes the
- * gradient outside the design region), 11 reserved.  With the fused y / z-sum kernels (TOF_OPT_FUSE_YZ) slot 2 (8 in
- * the adjoint) holds the fused kernel, slot 1 (7) is unused, and slot 3 (9)
- * holds the inverse y pass after a gather and is unused after a scatter.  At most 1024 calls are recorded between reads; later ones are not
- * timed.  Errors: TOF_ERR_INVALID, TOF_ERR_HIP.
+ * gradient outside the design region), 11 reserved.  With the fused y /
+ * z-sum kernels (TOF_OPT_FUSE_YZ) slot 2 (8 in the adjoint) holds the fused
+ * kernel, which also does the inverse y transform, and slots 1 and 3 (7 and
+ * 9) are unused.  At most 1024 calls are recorded between reads; later ones
+ * are not timed.  Errors: TOF_ERR_INVALID, TOF_ERR_HIP.
  */
 #define TOF_PROFILE_SLOTS 12
 tof_status tof_profile_enable(tof_ctx *ctx, int32_t enable);

@@ -251,10 +251,18 @@ void finish_product(ProductDev &pr)
 
 // ---- one convolution: five passes ----
 // slot0 = 0 for the forward convolution, 6 for the adjoint one.
+// Where a convolution stopped when its caller takes over the last pass: the
+// inverse x pass's input [c][kx][T.z][T.y] (nsum copies sum_stride apart).
+struct XTail {
+    const void *spec = nullptr;
+    int nsum = 1;
+    long long stride = 0;
+};
+
 template <typename R>
 tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const DesignDev<R> &dsg,
                     View4<const R> src, Box S, Box T, const ProductDev &prod, bool grad_epi, View4<R> out,
-                    const R *m0u, R *grad, bool a_ready = false)
+                    const R *m0u, R *grad, bool a_ready = false, XTail *tail = nullptr)
 {
     // the gradient epilogue (T = design box) also zeroes the gradient outside the design box
     const bool zero_rest = grad_epi;
@@ -297,11 +305,14 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         const int rows = gather ? S.nz() : T.nz();
         // enough blocks to fill the chip; the gather's partial rows must fit in B
         int G = std::max(1, std::min(rows, (kYzBlocks + hx - 1) / hx));
-        const long long part_rows = (long long)prod.c_out * hx * T.nz() * Ly;
+        // the gather's partial copies of the inverse x input (y space), added by that pass
+        const long long part_rows = (long long)prod.c_out * hx * T.nz() * T.ny();
         if (gather) G = (int)std::max(1LL, std::min<long long>(G, (long long)(ctx->B.bytes / sizeof(cplx<R>)) / part_rows));
         ya.rpg = (rows + G - 1) / G;
         G = (rows + ya.rpg - 1) / ya.rpg;
-        if (launch_yz_sum<R>(st, ya, kt, prod, ply, true) == hipSuccess) {
+        // the gather leaves G partial copies for the inverse x pass to add: register x lengths only
+        const bool x_reg = (ctx->Lx & (ctx->Lx - 1)) == 0 && ctx->Lx >= 32 && ctx->Lx <= 512;
+        if ((!gather || x_reg) && launch_yz_sum<R>(st, ya, kt, prod, ply, true) == hipSuccess) {
             const double part_bytes = (double)G * part_rows * cw;
             // the fused kernels read Kt for ky <= Ly/2 only (parity in y gives the rest)
             const double kt_half = ncomp * (double)hx * drows * (Ly / 2 + 1) * w;
@@ -309,16 +320,22 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                 HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_half + part_bytes, [&] {
                     return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
                 }));
-                const BlockMap flat{30, 0, 0};
-                HIP_TRY(ctx, timed(ctx, st, slot0 + 3, part_bytes + c_elems * cw, [&] {
-                    return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)T.nz() * Ly, Ly,
-                                              (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true, flat,
-                                              flat, G, part_rows);
+                if (tail) {
+                    *tail = XTail{B, G, part_rows};
+                    return TOF_OK;
+                }
+                HIP_TRY(ctx, timed(ctx, st, slot0 + 4, part_bytes + x_out, [&] {
+                    return launch_x_inverse<R>(st, B, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest,
+                                               G, part_rows);
                 }));
-            } else {
-                HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_half + c_elems * cw, [&] {
-                    return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
-                }));
+                return TOF_OK;
+            }
+            HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_half + c_elems * cw, [&] {
+                return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
+            }));
+            if (tail) {
+                *tail = XTail{C, 1, 0};
+                return TOF_OK;
             }
             HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
                 return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest);
@@ -346,6 +363,10 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)Zr * Ly, bm.row,
                                   (long long)T.nz() * T.ny(), T.ny(), 0, Ly, T.y0, T.ny(), ply, true, bm, plain);
     }));
+    if (tail) {
+        *tail = XTail{C, 1, 0};
+        return TOF_OK;
+    }
     HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
         return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest);
     }));
@@ -449,11 +470,11 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
     View4<R> hs{(R *)ctx->Hs.p, nob, (long long)ob.ny() * ob.nx(), ob.nx(), ob.x0, ob.y0, ob.z0};
     View4<const R> nosrc{};
     const R zero3[3] = {0, 0, 0};
-    tof_status s = convolve<R>(ctx, st, 0, ctx->m0f ? SRC_RHO_VECTOR : SRC_RHO_SCALAR, dsg, nosrc, ctx->design,
-                               ob, pf, false, hs, zero3, nullptr);
-    if (s != TOF_OK) return s;
+    const int mode = ctx->m0f ? SRC_RHO_VECTOR : SRC_RHO_SCALAR;
     if (ctx->opt_fuse_obj) {
-        // the objective fused with the adjoint's x pass: dJ/dH goes straight into A
+        // the forward stops before its inverse x pass; the objective kernel
+        // transforms the field rows it needs back along x itself, evaluates J
+        // and dJ/dH and transforms dJ/dH along x into A for the adjoint
         ObjectiveDev<R> o{ctx->kind, (const R *)ctx->Hs.p, ob, ctx->sensor, cj, nob,
                           ctx->sensor.nx() * ctx->sensor.ny() * ctx->sensor.nz(), ctx->target, ctx->lam, ctx->dx,
                           ctx->dy, ctx->dx * ctx->dy * ctx->dz, (const double *)ctx->Ht.p, J,
@@ -461,13 +482,25 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
         const FftPlanDev plx = ctx->px.dev(sizeof(R) == 8);
         cplx<R> *A = (cplx<R> *)ctx->A.p;
         if (launch_objective_xf<R>(st, o, plx, A, ctx->hx, true) == hipSuccess) {
+            XTail tail;
+            tof_status s = convolve<R>(ctx, st, 0, mode, dsg, nosrc, ctx->design, ob, pf, false, hs, zero3, nullptr,
+                                       false, &tail);
+            if (s != TOF_OK) return s;
             const double ht_bytes = ctx->kind == TOF_J_MEAN_SQ_H_TARGET ? 3.0 * o.S * 8.0 : 0.0;
-            const double fbytes = cj * nob * sizeof(R) + ht_bytes + 2.0 * sizeof(R) * cj * ctx->hx * ob.nz() * ob.ny();
-            HIP_TRY(ctx, timed(ctx, st, 5, fbytes, [&] { return launch_objective_xf<R>(st, o, plx, A, ctx->hx, false); }));
+            // the spectra of the pair and its stencil rows (up to 3x the pairs' rows), all copies; dJ/dH spectra out
+            const double rows_read = std::min(3.0 * ob.ny(), ob.ny() + 4.0 * ((ob.ny() + 1) / 2));
+            const double fbytes = tail.nsum * cj * ctx->hx * ob.nz() * rows_read * 2.0 * sizeof(R) + ht_bytes +
+                                  2.0 * sizeof(R) * cj * ctx->hx * ob.nz() * ob.ny();
+            HIP_TRY(ctx, timed(ctx, st, 5, fbytes, [&] {
+                return launch_objective_xf<R>(st, o, plx, A, ctx->hx, false, (const cplx<R> *)tail.spec, tail.nsum,
+                                              tail.stride);
+            }));
             View4<const R> nosrc2{};
             return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true);
         }
     }
+    tof_status s = convolve<R>(ctx, st, 0, mode, dsg, nosrc, ctx->design, ob, pf, false, hs, zero3, nullptr);
+    if (s != TOF_OK) return s;
     const double obytes = 2.0 * cj * nob * sizeof(R);
     HIP_TRY(ctx, timed(ctx, st, 5, obytes, [&] {
         return launch_objective<R>(st, ctx->kind, (const R *)ctx->Hs.p, ob, ctx->sensor, cj, ctx->target, ctx->lam,

@@ -103,7 +103,7 @@ constexpr int kZsumMaxRows = 4;
 template <typename R>
 struct YzSumArgs {
     const cplx<R> *A;        // x-pass output [c_in][hx][nzs][nys]
-    cplx<R> *part;           // gather: partial spectra [G][c_out][hx][nzt][Ly]
+    cplx<R> *part;           // gather: partial rows [G][c_out][hx][nzt][nyt] (y space)
     cplx<R> *C;              // scatter: inverse-x input [c_out][hx][nzt][nyt]
     int hx;
     int ys0, nys, zs0, nzs;  // source box rows
@@ -149,8 +149,9 @@ hipError_t launch_z_sum(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, i
                         const KtDev<R> &kt, const ProductDev &prod, BlockMap bm);
 
 // Passes 2-4 fused (yzsum.hip): the gather (nzt <= kZsumMaxRows) writes
-// partial spectra for an inverse y pass with nsum = ceil(nzs / rpg); the
-// scatter (nzs <= kZsumMaxRows) writes C.  Requires a power-of-two Ly in
+// G = ceil(nzs / rpg) partial copies of the inverse x input into `part`
+// (added by launch_x_inverse with nsum = G); the scatter (nzs <=
+// kZsumMaxRows) writes C.  Requires a power-of-two Ly in
 // [32, 512].  check_only: report whether the case is supported, launch nothing.
 template <typename R>
 hipError_t launch_yz_sum(hipStream_t st, const YzSumArgs<R> &a, const KtDev<R> &kt, const ProductDev &prod,
@@ -163,10 +164,13 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
 
 // zero_outside (with the gradient epilogue, T the design box): also zero the
 // gradient rows outside the design box, in the same launch where possible.
+// nsum > 1 (power-of-two Lx only): the input is the sum, in order, of nsum
+// copies sum_stride elements apart.
 template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
-                            const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside);
+                            const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside, int nsum = 1,
+                            long long sum_stride = 0);
 
 // blocks the objective kernel may use (partials buffer length)
 constexpr int kObjMaxBlocks = 1024;
@@ -188,14 +192,18 @@ struct ObjectiveDev {
 };
 
 // The objective fused with the first pass of the adjoint: per row pair of ob,
-// dJ/dH from Hs, the J terms of its sensor cells (block sums added in block
-// order by the last block), and the real-to-complex FFT along x of dJ/dH into
-// A ([c_j][hx][ob.nz][ob.ny], the x-pass layout with source box ob).  Needs a
-// power-of-two Lx in [32, 512] and at most kObjMaxBlocks row pairs, else
-// hipErrorInvalidValue; check_only: report, launch nothing.
+// dJ/dH from the field, the J terms of its sensor cells (block sums added in
+// block order by the last block), and the real-to-complex FFT along x of
+// dJ/dH into A ([c_j][hx][ob.nz][ob.ny], the x-pass layout with source box
+// ob).  The field comes from o.Hs (spec NULL) or, with spec, straight from
+// the forward convolution's inverse x input [c_j][hx][ob.nz][ob.ny] (nsum
+// copies sum_stride apart, added in order), transformed back along x here.
+// Needs a power-of-two Lx in [32, 512] and at most kObjMaxBlocks row pairs,
+// else hipErrorInvalidValue; check_only: report, launch nothing.
 template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
-                              bool check_only);
+                              bool check_only, const cplx<R> *spec = nullptr, int nsum = 1,
+                              long long sum_stride = 0);
 
 template <typename R>
 hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,

@@ -20,6 +20,9 @@
 #include "engine.h"
 #include "fft_reg.h"
 
+#ifndef TOF_X_WAVES_PER_EU
+#define TOF_X_WAVES_PER_EU 1
+#endif
 #ifndef TOF_ZSUM_U
 #define TOF_ZSUM_U 4
 #endif
@@ -597,21 +600,34 @@ __device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int c
     return v;
 }
 
-// Block: one row pair (y, y + 1) of ob at one z, one component; P threads.
-template <typename R, int L, int E>
-__global__ __launch_bounds__(L / E) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
-                                                        const cplx<R> *table)
+// Block: one row pair (y, y + 1) of ob at one z, one component; NLN lines
+// of P threads.  SPEC false: the field on ob is read from o.Hs.  SPEC true:
+// the field rows the pair needs (with the stencil's reach) come straight
+// from the forward convolution: line slot l transforms rows ty0 + 2l,
+// ty0 + 2l + 1 back along x from their kx spectra spec[g][cc][kx][zrel][y]
+// (nsum copies sum_stride apart, added in order), so the field is never
+// stored.
+template <typename R, int L, int E, bool SPEC>
+__global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
+                                                                         const cplx<R> *table, const cplx<R> *spec,
+                                                                         int nsum, long long sum_stride)
 {
     constexpr int P = L / E;
+    constexpr int NLN = SPEC ? 3 : 1;
+    constexpr int NTH = NLN * P;
+    constexpr int HX = L / 2 + 1;
     constexpr int PITCH = regfft::padded_len(L);
+    constexpr int AREA = PITCH > 2 * HX ? PITCH : 2 * HX;   // staging of a row pair's spectra, then the exchange
     constexpr int NT = regfft::twiddle_count(L, E);
-    __shared__ cplx<R> lds[PITCH];
+    __shared__ cplx<R> lds[NLN * AREA];
     __shared__ double red[P];
     __shared__ bool last;
     constexpr int TR = 6;   // tile rows: the pair and two more on each side (the stencil's reach)
     __shared__ R tile[TR * L];
     const Box &ob = o.ob;
-    const int p = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int l = line_of_thread<P>();
+    const int p = tid % P;
     const int cc = blockIdx.z;
     const int zrel = blockIdx.y;
     const int z = ob.z0 + zrel;
@@ -619,55 +635,120 @@ __global__ __launch_bounds__(L / E) void k_objective_xf(ObjectiveDev<R> o, cplx<
     const bool two = ybase + 1 < ob.y1;
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
-    // component cc of the field on rows ty0 .. ty1-1 of this z into LDS, all
-    // loads first (addresses clamped into ob)
+    // component cc of the field on rows ty0 .. ty1-1 of this z into LDS
     const int ty0 = max(ob.y0, ybase - 2), ty1 = min(ob.y1, ybase + 4), nx = ob.nx();
-    const R *plane = o.Hs + cc * o.nob + (long long)zrel * ob.ny() * nx;
-    R hv[TR * E];
+    if constexpr (!SPEC) {
+        // all loads first (addresses clamped into ob)
+        const R *plane = o.Hs + cc * o.nob + (long long)zrel * ob.ny() * nx;
+        R hv[TR * E];
 #pragma unroll
-    for (int it = 0; it < TR * E; ++it) {
-        const int e = p + P * it;
-        const int row = e / L, col = e % L;
-        hv[it] = plane[(long long)(min(ty0 + row, ty1 - 1) - ob.y0) * nx + min(col, nx - 1)];
+        for (int it = 0; it < TR * E; ++it) {
+            const int e = p + P * it;
+            const int row = e / L, col = e % L;
+            hv[it] = plane[(long long)(min(ty0 + row, ty1 - 1) - ob.y0) * nx + min(col, nx - 1)];
+        }
+#pragma unroll
+        for (int it = 0; it < TR * E; ++it) tile[p + P * it] = hv[it];
+    } else {
+        cplx<R> *area = lds + l * AREA;
+        const int ya = min(ty0 + 2 * l, ty1 - 1), yb = min(ty0 + 2 * l + 1, ty1 - 1);
+        const int nyt = ob.ny(), nzt = ob.nz();
+        // the row pair's spectra [h][k] (h = 0: row ya, 1: row yb), copies added in order
+        constexpr int NIT = (2 * HX + P - 1) / P;
+        const cplx<R> *base = spec + ((long long)cc * hx * nzt + zrel) * nyt;
+        cplx<R> w[NIT];
+        auto at = [&](int it) -> long long {
+            const int e = min(p + P * it, 2 * HX - 1);
+            const int k = e >> 1;
+            return (long long)k * nzt * nyt + ((e & 1) ? yb : ya) - ob.y0;
+        };
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) w[it] = base[at(it)];
+        for (int g = 1; g < nsum; ++g) {
+            cplx<R> u[NIT];
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) u[it] = base[g * sum_stride + at(it)];
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) w[it] = cadd(w[it], u[it]);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = p + P * it;
+            if (e < 2 * HX) area[(e & 1) * HX + (e >> 1)] = w[it];
+        }
+        regfft::exchange_sync<true>();
+        // two real rows in one complex line: Z = X_a + i X_b, X_b from the odd spectrum
+        cplx<R> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int k = p + P * m;
+            cplx<R> a, b;
+            if (k <= L / 2) {
+                a = area[k];
+                b = area[HX + k];
+                if (k == 0 || k == L / 2) {
+                    a.y = 0;
+                    b.y = 0;
+                }
+            } else {
+                a = cconj(area[L - k]);
+                b = cconj(area[HX + L - k]);
+            }
+            v[m] = cplx<R>{a.x - b.y, a.y + b.x};
+        }
+        regfft::exchange_sync<true>();
+        regfft::fft_line<R, L, E, true>(v, tw, area, p, true);
+        if (ty0 + 2 * l < ty1) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int x = p + P * m;
+                if (x < ob.x0 || x >= ob.x1) continue;
+                tile[(2 * l) * L + (x - ob.x0)] = v[m].x;
+                if (ty0 + 2 * l + 1 < ty1) tile[(2 * l + 1) * L + (x - ob.x0)] = v[m].y;
+            }
+        }
     }
-#pragma unroll
-    for (int it = 0; it < TR * E; ++it) tile[p + P * it] = hv[it];
     __syncthreads();
     auto H = [&](int x, int y) -> double {
         const int row = min(max(y, ty0), ty1 - 1) - ty0;
         return (double)tile[row * L + min(max(x - ob.x0, 0), nx - 1)];
     };
+    // dJ/dH on the pair and the J terms of its sensor cells: line slot 0
     cplx<R> v[E];
     double jsum = 0.0;
+    if (l == 0) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int x = p + P * m;
-        double ja = 0.0, jb = 0.0, ga = 0.0, gb = 0.0;
-        if (x >= ob.x0 && x < ob.x1) {
-            ga = objective_cell(o, cc, x, ybase, z, H, ja);
-            if (two) gb = objective_cell(o, cc, x, ybase + 1, z, H, jb);
+        for (int m = 0; m < E; ++m) {
+            const int x = p + P * m;
+            double ja = 0.0, jb = 0.0, ga = 0.0, gb = 0.0;
+            if (x >= ob.x0 && x < ob.x1) {
+                ga = objective_cell(o, cc, x, ybase, z, H, ja);
+                if (two) gb = objective_cell(o, cc, x, ybase + 1, z, H, jb);
+            }
+            jsum += ja;
+            jsum += jb;
+            v[m] = cplx<R>{(R)ga, (R)gb};
         }
-        jsum += ja;
-        jsum += jb;
-        v[m] = cplx<R>{(R)ga, (R)gb};
     }
-    // the block's J terms, in a fixed order
-    red[p] = jsum;
+    // the block's J terms (all in line slot 0), in a fixed order
+    if (l == 0) red[p] = jsum;
     __syncthreads();
     for (int w = P / 2; w > 0; w >>= 1) {
-        if (p < w) red[p] += red[p + w];
+        if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
-    regfft::fft_line<R, L, E, true>(v, tw, lds, p, false);
+    if (l == 0) {
+        regfft::fft_line<R, L, E, true>(v, tw, lds, p, false);
 #pragma unroll
-    for (int m = 0; m < E; ++m) lds[regfft::swz(p + P * m)] = v[m];
+        for (int m = 0; m < E; ++m) lds[regfft::swz(p + P * m)] = v[m];
+    }
     __syncthreads();
     // split the pair: row y from the even part, row y + 1 from the odd part
     const int nys = ob.ny(), nzs = ob.nz();
     const long long kxs = (long long)nzs * nys;
     cplx<R> *dst = out + (long long)cc * hx * kxs + (long long)zrel * nys + (ybase - ob.y0);
     const R half = (R)0.5;
-    for (int e = p; e < 2 * hx; e += P) {
+    for (int e = tid; e < 2 * hx; e += NTH) {
         const int k = e >> 1, r = e & 1;
         if (r == 1 && !two) continue;
         const cplx<R> Zk = lds[regfft::swz(k)];
@@ -678,7 +759,7 @@ __global__ __launch_bounds__(L / E) void k_objective_xf(ObjectiveDev<R> o, cplx<
     // J: the last block to finish adds the block sums in block order
     const int nb = gridDim.x * gridDim.y * gridDim.z;
     const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    if (p == 0) {
+    if (tid == 0) {
         o.partials[bid] = red[0];
         __threadfence();
         last = atomicAdd(o.ticket, 1u) == (unsigned int)(nb - 1);
@@ -688,9 +769,9 @@ __global__ __launch_bounds__(L / E) void k_objective_xf(ObjectiveDev<R> o, cplx<
         // the block sums into LDS by all threads at once, then added in block order
         __shared__ double sums[kObjMaxBlocks];
         __threadfence();
-        for (int b = p; b < nb; b += P) sums[b] = o.partials[b];
+        for (int b = tid; b < nb; b += NTH) sums[b] = o.partials[b];
         __syncthreads();
-        if (p == 0) {
+        if (tid == 0) {
             double total = 0.0;
             for (int b = 0; b < nb; ++b) total += sums[b];
             *o.J = o.kind == 4 ? -0.5 * o.vcell * total : total / (double)o.S;
@@ -1171,7 +1252,7 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 // Block: NLC complex lines = 2 NLC source rows of one z (and one component);
 // each thread transforms LPT of them in turn.
 template <typename R, int L, int E, int NLC, int LPT>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_X_WAVES_PER_EU))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
                                                                 Box S, cplx<R> *out, int hx, const cplx<R> *table)
 {
     constexpr int P = L / E;
@@ -1295,10 +1376,11 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xf_reg(int mode, Desi
 // -- pass 5: complex-to-real inverse FFT along x + epilogue -----------------
 // Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
 // each thread transforms LPT lines in turn.
-template <typename R, int L, int E, int NLC, int LPT, int CO>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
+template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_X_WAVES_PER_EU))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
                                                                 View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
-                                                                R m0u2, R *grad, const cplx<R> *table, int zrows)
+                                                                R m0u2, R *grad, const cplx<R> *table, int zrows,
+                                                                int nsum, long long sum_stride)
 {
     if ((int)blockIdx.y >= T.nz()) {
         // blocks past the target rows zero the gradient rows outside the design
@@ -1348,17 +1430,39 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) void k_xi_reg(const cplx<R> 
         const cplx<R> *src = C + ((long long)(cc * hx + k0) * nzt + zrel) * nyt + (ybase - T.y0 + min(r, nrow - 1));
         const long long sstep = (long long)KSTEP * nzt * nyt;
         cplx<R> stg[NIT];
+        const int itmax = (hx - 1 - k0) / KSTEP;   // rows past nrow and frequencies past hx read a clamped address
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) stg[it] = src[min(it, itmax) * sstep];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int k = k0 + it * KSTEP;
-            // rows past nrow and frequencies past hx read a clamped address
-            const cplx<R> a = src[min(it, (hx - 1 - k0) / KSTEP) * sstep];
-            stg[it] = (k < HX && r < nrow) ? a : cplx<R>{0, 0};
+            if (k < HX) lds[r * HX + k] = (r < nrow) ? stg[it] : cplx<R>{0, 0};
         }
+        // partial copies of the input (PS), added in order in LDS (each thread
+        // updates only its own elements)
+        // up to 8 copies per round, all their loads in flight together
+        constexpr int GU = PS ? 8 : 1;
+        for (int g0 = 1; PS && g0 < nsum; g0 += GU) {
+            cplx<R> w[GU][NIT];
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int k = k0 + it * KSTEP;
-            if (k < HX) lds[r * HX + k] = stg[it];
+            for (int u = 0; u < GU; ++u) {
+                const cplx<R> *sg = src + min(g0 + u, nsum - 1) * sum_stride;
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const cplx<R> a = sg[min(it, itmax) * sstep];
+                    w[u][it] = g0 + u < nsum ? a : cplx<R>{0, 0};
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int k = k0 + it * KSTEP;
+                if (k < HX && r < nrow) {
+                    cplx<R> acc = lds[r * HX + k];
+#pragma unroll
+                    for (int u = 0; u < GU; ++u) acc = cadd(acc, w[u][it]);
+                    lds[r * HX + k] = acc;
+                }
+            }
         }
         __syncthreads();
         cplx<R> v[LPT][E];
@@ -1670,50 +1774,56 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
 
 template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T, const FftPlanDev &plan,
-                         bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad, int zrows)
+                         bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad, int zrows,
+                         int nsum, long long sum_stride)
 {
     constexpr int E = 8;
     if ((long long)((T.ny() + 2 * NLC - 1) / (2 * NLC)) * T.nz() < 512 && NLC > 1)
-        return launch_xi_reg<R, L, 1, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
+        return launch_xi_reg<R, L, 1, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum,
+                                         sum_stride);
     const int gx = (T.ny() + 2 * NLC - 1) / (2 * NLC);
     // extra block rows for the zero fill, kZeroRowsPerBlock rows each
     const int gz = (int)((zrows + (long long)gx * kZeroRowsPerBlock - 1) / ((long long)gx * kZeroRowsPerBlock));
     dim3 grid(gx, T.nz() + gz);
     dim3 block((NLC / LPT) * (L / E));
-    if (c == 1)
-        TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, 1>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
-                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows);
-    else if (c == 3)
-        TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, 3>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out,
-                           dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows);
-    else
-        return hipErrorInvalidValue;
+#define TOF_XI_LAUNCH(CC, PSV)                                                                                   \
+    TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, CC, PSV>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out, dsg, \
+               m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows, nsum, sum_stride)
+    if (c == 1 && nsum == 1) TOF_XI_LAUNCH(1, false);
+    else if (c == 1) TOF_XI_LAUNCH(1, true);
+    else if (c == 3 && nsum == 1) TOF_XI_LAUNCH(3, false);
+    else if (c == 3) TOF_XI_LAUNCH(3, true);
+    else return hipErrorInvalidValue;
+#undef TOF_XI_LAUNCH
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
-                            const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside)
+                            const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside, int nsum,
+                            long long sum_stride)
 {
+    if (nsum < 1) return hipErrorInvalidValue;
     const long long zr = grad_epilogue && zero_outside ? outside_rows(dsg.ny, dsg.nz, dsg.design) : 0;
     if (zr > (1LL << 30)) return hipErrorInvalidValue;
     const int zrows = (int)zr;
     if (c == 1 || c == 3) {
         switch (plan.L) {
-        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
-        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
+        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
+        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
         case 128:
-            return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows);
+            return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
         case 256:
             return launch_xi_reg<R, 256, TOF_X_NLC256, TOF_X_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
-                                                                    grad, zrows);
+                                                                    grad, zrows, nsum, sum_stride);
         case 512:
             return launch_xi_reg<R, 512, TOF_X_NLC512, TOF_X_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
-                                                                    grad, zrows);
+                                                                    grad, zrows, nsum, sum_stride);
         default: break;
         }
     }
+    if (nsum != 1) return hipErrorInvalidValue;   // partial copies: register lengths only
     const int pitch = plan.L + 2;
     const size_t per_line = 2 * (size_t)c * pitch * sizeof(cplx<R>);
     int TY = 2 * (int)(kLdsBudget / per_line);
@@ -1732,17 +1842,21 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
 
 template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
-                              bool check_only)
+                              bool check_only, const cplx<R> *spec, int nsum, long long sum_stride)
 {
     const long long nb = (long long)((o.ob.ny() + 1) / 2) * o.ob.nz() * o.c_j;
-    if (nb < 1 || nb > kObjMaxBlocks || o.ob.nz() > 65535) return hipErrorInvalidValue;
+    if (nb < 1 || nb > kObjMaxBlocks || o.ob.nz() > 65535 || nsum < 1) return hipErrorInvalidValue;
     constexpr int E = 8;
     const dim3 grid((o.ob.ny() + 1) / 2, o.ob.nz(), o.c_j);
     const cplx<R> *tw = (const cplx<R> *)plan.tw;
-#define TOF_OBJ_CASE(LL)                                                                     \
-    case LL:                                                                                 \
-        if (check_only) return hipSuccess;                                                   \
-        TOF_LAUNCH((k_objective_xf<R, LL, E>), grid, dim3(LL / E), 0, st, o, A, hx, tw);     \
+#define TOF_OBJ_CASE(LL)                                                                                     \
+    case LL:                                                                                                 \
+        if (check_only) return hipSuccess;                                                                   \
+        if (spec)                                                                                            \
+            TOF_LAUNCH((k_objective_xf<R, LL, E, true>), grid, dim3(3 * (LL / E)), 0, st, o, A, hx, tw, spec, \
+                       nsum, sum_stride);                                                                    \
+        else                                                                                                 \
+            TOF_LAUNCH((k_objective_xf<R, LL, E, false>), grid, dim3(LL / E), 0, st, o, A, hx, tw, spec, 1, 0LL); \
         return hipGetLastError();
     switch (plan.L) {
         TOF_OBJ_CASE(32)
@@ -1888,9 +2002,9 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                          const FftPlanDev &, BlockMap);                                  \
     template hipError_t launch_x_inverse<R>(hipStream_t, const cplx<R> *, int, int, Box,                 \
                                             const FftPlanDev &, bool, View4<R>, const DesignDev<R> &,    \
-                                            const R *, R *, bool);                                       \
+                                            const R *, R *, bool, int, long long);                       \
     template hipError_t launch_objective_xf<R>(hipStream_t, const ObjectiveDev<R> &, const FftPlanDev &,  \
-                                               cplx<R> *, int, bool);                                     \
+                                               cplx<R> *, int, bool, const cplx<R> *, int, long long);    \
     template hipError_t launch_objective<R>(hipStream_t, int, const R *, Box, Box, int, double, double,  \
                                             double, double, double, const double *, double *, R *,       \
                                             double *, unsigned int *);                                   \

@@ -6,12 +6,12 @@
 // y spectra of those rows never go through HBM.
 //
 //   gather  (few target rows): per kx, the y FFT of every source row times
-//           Kt, summed over the source rows of a group; each group's sum is
-//           a partial spectrum row, and the inverse y pass adds the partials
-//           (in group order) before transforming.  (Adding them in the last
-//           block of each kx instead needs a device-scope release per block,
-//           an L2 write-back on this chip, which costs far more than the
-//           separate pass.)
+//           Kt, summed over the source rows of a group and transformed back
+//           along y; each group writes its partial target rows in y space,
+//           and the inverse x pass adds the partials (in group order) while
+//           staging.  (Adding them in the last block of each kx instead
+//           needs a device-scope release per block, an L2 write-back on this
+//           chip, which costs far more.)
 //   scatter (few source rows): per kx, the y FFT of the source rows (kept in
 //           LDS), then for every target row the sum against Kt and the
 //           inverse y FFT, written straight into the layout of the inverse x
@@ -28,6 +28,10 @@
 namespace {
 
 using namespace tofdev;
+
+#ifndef TOF_YZ_WAVES_PER_EU
+#define TOF_YZ_WAVES_PER_EU 1
+#endif
 
 constexpr int kE = 8;           // elements per thread of a y line
 constexpr int kBlock = 256;     // threads per block
@@ -94,11 +98,12 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
 
 // Few target rows.  Block (kx, g) takes source rows [g rpg, (g+1) rpg) of
 // the source box; line slot l transforms rows l, l + NL, ... of that range.
-// A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][L].
+// A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][nyt]
+// with y from yt0: G copies of the inverse x pass's input, to be added.
 template <typename R, int L, int E, int CI, int CO, int NC, int NR>
-__global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
-                                                         int zt0, int nzt, int rpg, KtDev<R> kt, ProductDev prod,
-                                                         cplx<R> *part, const cplx<R> *table)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_WAVES_PER_EU))) void k_yzsum_gather(
+    const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
+    KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table)
 {
     constexpr int P = L / E;
     constexpr int NL = kBlock / P;
@@ -150,7 +155,8 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int h
                 if (r < nzt) zsum_mac<R, CI, CO, NC>(prod, K[r][m], xm, acc[r][m]);
         }
     }
-    // the slots' sums, added in slot order
+    // the slots' sums, added in slot order by the first slot, transformed
+    // back along y there: the group's partial rows of the target in y space
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (r >= nzt) break;
@@ -160,11 +166,22 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int h
 #pragma unroll
             for (int m = 0; m < E; ++m) my[p + P * m] = acc[r][m][o];
             __syncthreads();
-            cplx<R> *dst = part + (((long long)(blockIdx.y * CO + o) * hx + kx) * nzt + r) * L;
-            for (int q = threadIdx.x; q < L; q += kBlock) {
-                cplx<R> s = lds[q];
-                for (int sl = 1; sl < NL; ++sl) s = cadd(s, lds[sl * PITCH + q]);
-                dst[q] = s;
+            if (l == 0) {
+                cplx<R> v[E];
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    cplx<R> s = lds[p + P * m];
+                    for (int sl = 1; sl < NL; ++sl) s = cadd(s, lds[sl * PITCH + p + P * m]);
+                    v[m] = s;
+                }
+                // every lane has read its sums before the first exchange write (one wave)
+                regfft::fft_line<R, L, E, true>(v, tw, lds, p, true);
+                cplx<R> *dst = part + (((long long)(blockIdx.y * CO + o) * hx + kx) * nzt + r) * nyt - yt0;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int n = p + P * m;
+                    if (n >= yt0 && n < yt0 + nyt) dst[n] = v[m];
+                }
             }
         }
     }
@@ -175,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_yzsum_gather(const cplx<R> *A, int h
 // A is [CI][hx][nzs][nys]; C is [CO][hx][nzt][nyt] with y from yt0 (the
 // input layout of the inverse x pass).
 template <typename R, int L, int E, int CI, int CO, int NC, int NR>
-__global__ __launch_bounds__(kBlock) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_WAVES_PER_EU))) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
                                                           int zt0, int nzt, int rpg, int yt0, int nyt, KtDev<R> kt,
                                                           ProductDev prod, cplx<R> *C, const cplx<R> *table)
 {
@@ -286,14 +303,14 @@ hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
+                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table);
                 return hipGetLastError();
             }
         } else {
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, kt, prod, a.part, table);
+                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table);
                 return hipGetLastError();
             }
         }
