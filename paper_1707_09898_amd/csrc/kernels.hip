@@ -587,15 +587,17 @@ __device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int c
     jterm = in ? d * d : 0.0;
     if (o.kind == 2) {
         // central differences at this cell (its J term) and at the four sensor
-        // neighbours whose differences read this cell (the transpose)
-        const double gx = (H(x + 1, y) - H(x - 1, y)) / (2.0 * o.dx);
-        const double gy = (H(x, y + 1) - H(x, y - 1)) / (2.0 * o.dy);
+        // neighbours whose differences read this cell (the transpose); the
+        // divisions by 2 dx, 2 dy as products with their reciprocals
+        const double rx = 0.5 / o.dx, ry = 0.5 / o.dy;
+        const double gx = (H(x + 1, y) - H(x - 1, y)) * rx;
+        const double gy = (H(x, y + 1) - H(x, y - 1)) * ry;
         if (in) jterm += o.lam * (gx * gx + gy * gy);
         const double cxs = o.lam * invS / o.dx, cys = o.lam * invS / o.dy;
-        if (sb.has(x - 1, y, z)) v += cxs * ((h - H(x - 2, y)) / (2.0 * o.dx));
-        if (sb.has(x + 1, y, z)) v -= cxs * ((H(x + 2, y) - h) / (2.0 * o.dx));
-        if (sb.has(x, y - 1, z)) v += cys * ((h - H(x, y - 2)) / (2.0 * o.dy));
-        if (sb.has(x, y + 1, z)) v -= cys * ((H(x, y + 2) - h) / (2.0 * o.dy));
+        if (sb.has(x - 1, y, z)) v += cxs * ((h - H(x - 2, y)) * rx);
+        if (sb.has(x + 1, y, z)) v -= cxs * ((H(x + 2, y) - h) * rx);
+        if (sb.has(x, y - 1, z)) v += cys * ((h - H(x, y - 2)) * ry);
+        if (sb.has(x, y + 1, z)) v -= cys * ((H(x, y + 2) - h) * ry);
     }
     return v;
 }
@@ -664,12 +666,23 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
         };
 #pragma unroll
         for (int it = 0; it < NIT; ++it) w[it] = base[at(it)];
-        for (int g = 1; g < nsum; ++g) {
-            cplx<R> u[NIT];
+        // up to 8 further copies per round, their loads in flight together
+        constexpr int GU = 8;
+        for (int g0 = 1; g0 < nsum; g0 += GU) {
+            cplx<R> u[GU][NIT];
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) u[it] = base[g * sum_stride + at(it)];
+            for (int q = 0; q < GU; ++q) {
+                const cplx<R> *bg = base + min(g0 + q, nsum - 1) * sum_stride;
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) w[it] = cadd(w[it], u[it]);
+                for (int it = 0; it < NIT; ++it) {
+                    const cplx<R> a = bg[at(it)];
+                    u[q][it] = g0 + q < nsum ? a : cplx<R>{0, 0};
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < GU; ++q)
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) w[it] = cadd(w[it], u[q][it]);
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
