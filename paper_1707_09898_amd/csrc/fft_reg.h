@@ -189,6 +189,70 @@ __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R
     }
 }
 
+// NV independent lines at once (line j: v[j][m], exchange area lds + j
+// area): each stage runs for all lines between the same two syncs, which
+// halves the syncs per line and gives the scheduler independent work.
+template <typename R, int L, int E, int S, int NV, bool WAVE>
+__device__ __forceinline__ void fft_stages_n(cplx<R> (*v)[E], const cplx<R> *tw, cplx<R> *lds, int area, int p,
+                                             bool inv)
+{
+    constexpr int P = L / E;
+    constexpr int NS = num_stages(L, E);
+    if constexpr (S < NS) {
+        constexpr int Rr = stage_radix(L, E, S);
+        constexpr int Ns = stage_ns(L, E, S);
+        constexpr bool last = (S == NS - 1);
+        constexpr int at = [] {
+            int n = 0;
+            for (int q = 1; q < S; ++q) n += (E / stage_radix(L, E, q)) * (stage_radix(L, E, q) - 1);
+            return n;
+        }();
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+#pragma unroll
+            for (int b = 0; b < E / Rr; ++b) {
+                cplx<R> u[Rr];
+#pragma unroll
+                for (int r = 0; r < Rr; ++r) u[r] = v[j][b + r * (E / Rr)];
+                if constexpr (S > 0) {
+#pragma unroll
+                    for (int r = 1; r < Rr; ++r) {
+                        cplx<R> w = tw[at + b * (Rr - 1) + (r - 1)];
+                        if (inv) w.y = -w.y;
+                        u[r] = cmul(u[r], w);
+                    }
+                }
+                dft_pow2<R, Rr>(u, inv);
+                if constexpr (last) {
+#pragma unroll
+                    for (int r = 0; r < Rr; ++r) v[j][b + r * (E / Rr)] = u[r];
+                } else {
+                    const int jj = p + P * b;
+                    const int base = (jj / Ns) * (Ns * Rr) + (jj & (Ns - 1));
+#pragma unroll
+                    for (int r = 0; r < Rr; ++r) lds[j * area + swz(base + r * Ns)] = u[r];
+                }
+            }
+        }
+        if constexpr (!last) {
+            exchange_sync<WAVE>();
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+                for (int m = 0; m < E; ++m) v[j][m] = lds[j * area + swz(p + P * m)];
+            exchange_sync<WAVE>();
+            fft_stages_n<R, L, E, S + 1, NV, WAVE>(v, tw, lds, area, p, inv);
+        }
+    }
+}
+
+template <typename R, int L, int E, int NV, bool WAVE = false>
+__device__ __forceinline__ void fft_lines(cplx<R> (*v)[E], const cplx<R> *tw, cplx<R> *lds, int area, int p, bool inv)
+{
+    static_assert(!WAVE || 64 % (L / E) == 0, "a wave-synchronized line must lie inside one wave");
+    fft_stages_n<R, L, E, 0, NV, WAVE>(v, tw, lds, area, p, inv);
+}
+
 // Transform one line held as v[m] = x[p + P m] by thread p.  `lds` is this
 // line's exchange area (padded_len(L) complex; position i at swz(i)).  With
 // WAVE false all threads of the block call it together (it contains block

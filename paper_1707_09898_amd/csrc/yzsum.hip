@@ -32,6 +32,9 @@ using namespace tofdev;
 #ifndef TOF_YZ_WAVES_PER_EU
 #define TOF_YZ_WAVES_PER_EU 1
 #endif
+#ifndef TOF_YZ_ROWS
+#define TOF_YZ_ROWS 1
+#endif
 
 constexpr int kE = 8;           // elements per thread of a y line
 constexpr int kBlock = 256;     // threads per block
@@ -201,7 +204,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
     constexpr int PITCH = regfft::padded_len(L);
     constexpr int NT = regfft::twiddle_count(L, E);
     constexpr int NQ = NR * CI;
-    __shared__ cplx<R> lds[NL * PITCH];
+    constexpr int NV = TOF_YZ_ROWS;   // target rows a slot transforms together
+    __shared__ cplx<R> lds[NV * NL * PITCH];
     __shared__ cplx<R> xs[NQ * L];   // source spectra, line q = r CI + i
     const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
@@ -226,51 +230,59 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
     }
     __syncthreads();
     const int ra = blockIdx.y * rpg, rb = min(ra + rpg, nzt);
-    const int nit = (rb - ra + NL - 1) / NL;
+    // slot l takes rows ra + l + NL (NV it + v), v < NV, per iteration it
+    const int nit = (rb - ra + NV * NL - 1) / (NV * NL);
     constexpr int H = E / 2;
     // the tensor values of iteration `it`, loaded one iteration ahead
-    R Kh[NR][H + 1][NC];
-    auto fetch = [&](int it, R (*Kf)[H + 1][NC]) {
-        const int zrc = min(ra + it * NL + l, rb - 1);
+    R Kh[NV][NR][H + 1][NC];
+    auto fetch = [&](int it, R (*Kf)[NR][H + 1][NC]) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            kt_half<R, L, E, NC>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), Kf[r]);
+        for (int v = 0; v < NV; ++v) {
+            const int zrc = min(ra + (NV * it + v) * NL + l, rb - 1);
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                kt_half<R, L, E, NC>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), Kf[v][r]);
+        }
     };
     fetch(0, Kh);
     for (int it = 0; it < nit; ++it) {
-        const int zr = ra + it * NL + l;
-        const bool ok = zr < rb;
-        const int zrc = min(zr, rb - 1);
-        R K[NR][E][NC];
+        R K[NV][NR][E][NC];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC>(prod, p, Kh[r], K[r]);
-        fetch(it + 1, Kh);   // unconditional, see the gather
-        cplx<R> Y[CO][E];
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            cplx<R> out[CO];
-#pragma unroll
-            for (int o = 0; o < CO; ++o) out[o] = cplx<R>{0, 0};
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                if (r >= nzs) break;
-                cplx<R> xm[CI];
-#pragma unroll
-                for (int i = 0; i < CI; ++i) xm[i] = xs[(r * CI + i) * L + p + P * m];
-                zsum_mac<R, CI, CO, NC>(prod, K[r][m], xm, out);
-            }
-#pragma unroll
-            for (int o = 0; o < CO; ++o) Y[o][m] = out[o];
-        }
+            for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC>(prod, p, Kh[v][r], K[v][r]);
+        fetch(it + 1, Kh);   // unconditional: a conditional fetch would be waited for before the transforms
 #pragma unroll
         for (int o = 0; o < CO; ++o) {
-            regfft::fft_line<R, L, E, true>(Y[o], tw, my, p, true);
-            if (ok) {
-                cplx<R> *dst = C + (((long long)o * hx + kx) * nzt + zrc) * nyt - yt0;
+            cplx<R> Y[NV][E];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
-                    const int n = p + P * m;
-                    if (n >= yt0 && n < yt0 + nyt) dst[n] = Y[o][m];
+                    cplx<R> out[CO];
+#pragma unroll
+                    for (int oo = 0; oo < CO; ++oo) out[oo] = cplx<R>{0, 0};
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        if (r >= nzs) break;
+                        cplx<R> xm[CI];
+#pragma unroll
+                        for (int i = 0; i < CI; ++i) xm[i] = xs[(r * CI + i) * L + p + P * m];
+                        zsum_mac<R, CI, CO, NC>(prod, K[v][r][m], xm, out);
+                    }
+                    Y[v][m] = out[o];
+                }
+            regfft::fft_lines<R, L, E, NV, true>(Y, tw, my, NL * PITCH, p, true);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int zr = ra + (NV * it + v) * NL + l;
+                if (zr < rb) {
+                    cplx<R> *dst = C + (((long long)o * hx + kx) * nzt + zr) * nyt - yt0;
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const int n = p + P * m;
+                        if (n >= yt0 && n < yt0 + nyt) dst[n] = Y[v][m];
+                    }
                 }
             }
         }
@@ -283,11 +295,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
 constexpr bool gather_fits(int CO, int NC, int NR) { return NR * CO <= 4 && NR * NC <= 6; }
 constexpr size_t scatter_lds(int L, int CI, int NR, size_t csz)
 {
-    return ((size_t)(kBlock / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
+    return ((size_t)TOF_YZ_ROWS * (kBlock / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
 }
 constexpr bool scatter_fits(int L, int CI, int NC, int NR, size_t csz)
 {
-    return NR * NC <= 6 && scatter_lds(L, CI, NR, csz) <= 64 * 1024;
+    return NR * NC <= 6 && scatter_lds(L, CI, NR, csz) <= 96 * 1024;
 }
 
 template <typename R, int L, int CI, int CO, int NC>
