@@ -94,7 +94,14 @@ struct tof_ctx {
 namespace {
 
 constexpr int kProfCalls = 1024;
-constexpr int kYzBlocks = 2048;   // blocks a fused y / z-sum launch aims for (several per CU)
+// Row groups of the fused y / z-sum kernels (blocks = groups x (Lx/2+1)):
+// 8 measured best at 256x256x128 among 4, 7, 8, 15 and 31.
+#ifndef TOF_YZ_GATHER_GROUPS
+#define TOF_YZ_GATHER_GROUPS 8
+#endif
+#ifndef TOF_YZ_SCATTER_GROUPS
+#define TOF_YZ_SCATTER_GROUPS 8
+#endif
 
 tof_status fail(tof_ctx *ctx, tof_status st, const std::string &msg)
 {
@@ -303,8 +310,8 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         YzSumArgs<R> ya{A, B, C, hx, S.y0, S.ny(), S.z0, S.nz(), T.y0, T.ny(), T.z0, T.nz(), 1};
         const bool gather = T.nz() <= kZsumMaxRows;
         const int rows = gather ? S.nz() : T.nz();
-        // enough blocks to fill the chip; the gather's partial rows must fit in B
-        int G = std::max(1, std::min(rows, (kYzBlocks + hx - 1) / hx));
+        // the gather's partial rows must fit in B
+        int G = std::max(1, std::min(rows, gather ? TOF_YZ_GATHER_GROUPS : TOF_YZ_SCATTER_GROUPS));
         // the gather's partial copies of the inverse x input (y space), added by that pass
         const long long part_rows = (long long)prod.c_out * hx * T.nz() * T.ny();
         if (gather) G = (int)std::max(1LL, std::min<long long>(G, (long long)(ctx->B.bytes / sizeof(cplx<R>)) / part_rows));

@@ -129,14 +129,11 @@ template <typename R>
 hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
                             Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx);
 
-// nsum > 1 (power-of-two lengths only): the input line is the sum, in order,
-// of nsum lines sum_stride elements apart.
 template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
                            long long out_inner, int p_in, int n_in, int p_out, int n_out,
-                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout, int nsum = 1,
-                           long long sum_stride = 0);
+                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout);
 
 template <typename R>
 hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, int zs0, int nzs,

@@ -944,7 +944,7 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
                                                         long long in_outer, long long in_inner, long long out_outer,
                                                         long long out_inner, int p_in, int n_in, int p_out,
                                                         int n_out, const cplx<R> *table, int inv, BlockMap bin,
-                                                        BlockMap bout, int nsum, long long sum_stride)
+                                                        BlockMap bout)
 {
     constexpr int P = L / E;
     constexpr int PITCH = regfft::padded_len(L);
@@ -959,19 +959,9 @@ __global__ __launch_bounds__(NL *(L / E)) void k_line_reg(const cplx<R> *in, cpl
     cplx<R> v[E];
     const int lc = live ? line : 0;   // a dead slot reads line 0 and stores nothing
     const long long ib = (long long)(lc / inner) * in_outer + (long long)(lc % inner) * in_inner;
-    long long at[E];
+    // addresses clamped into the line: every load issued before the first use
 #pragma unroll
-    for (int m = 0; m < E; ++m) at[m] = ib + bin.at(min(max(p + P * m - p_in, 0), n_in - 1));
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = in[at[m]];
-    // partial lines added in order
-    for (int g = 1; g < nsum; ++g) {
-        cplx<R> w[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) w[m] = in[at[m] + g * sum_stride];
-#pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = cadd(v[m], w[m]);
-    }
+    for (int m = 0; m < E; ++m) v[m] = in[ib + bin.at(min(max(p + P * m - p_in, 0), n_in - 1))];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int n = p + P * m;
@@ -1663,7 +1653,7 @@ template <typename R, int L>
 hipError_t launch_line_reg(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer, long long out_inner,
                            int p_in, int n_in, int p_out, int n_out, const FftPlanDev &plan, bool inv, BlockMap bin,
-                           BlockMap bout, int nsum, long long sum_stride)
+                           BlockMap bout)
 {
     constexpr int E = 8;
     constexpr int NL = 256 / (L / E);
@@ -1671,13 +1661,13 @@ hipError_t launch_line_reg(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
         // few lines (the sensor plane): one line per block spreads them over more CUs
         TOF_LAUNCH((k_line_reg<R, L, E, 1>), dim3(nlines), dim3(L / E), 0, st, in, out, nlines, inner,
                            in_outer, in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out,
-                           (const cplx<R> *)plan.tw, inv ? 1 : 0, bin, bout, nsum, sum_stride);
+                           (const cplx<R> *)plan.tw, inv ? 1 : 0, bin, bout);
         return hipGetLastError();
     }
     dim3 grid((nlines + NL - 1) / NL);
     TOF_LAUNCH((k_line_reg<R, L, E, NL>), grid, dim3(256), 0, st, in, out, nlines, inner, in_outer,
                        in_inner, out_outer, out_inner, p_in, n_in, p_out, n_out, (const cplx<R> *)plan.tw,
-                       inv ? 1 : 0, bin, bout, nsum, sum_stride);
+                       inv ? 1 : 0, bin, bout);
     return hipGetLastError();
 }
 
@@ -1685,15 +1675,13 @@ template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
                            long long in_outer, long long in_inner, long long out_outer,
                            long long out_inner, int p_in, int n_in, int p_out, int n_out,
-                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout, int nsum,
-                           long long sum_stride)
+                           const FftPlanDev &plan, bool inv, BlockMap bin, BlockMap bout)
 {
     if (nlines <= 0) return hipSuccess;
-    if (nsum < 1) return hipErrorInvalidValue;
 #define TOF_LINE_CASE(LL)                                                                                    \
     case LL:                                                                                                 \
         return launch_line_reg<R, LL>(st, in, out, nlines, inner, in_outer, in_inner, out_outer, out_inner, \
-                                      p_in, n_in, p_out, n_out, plan, inv, bin, bout, nsum, sum_stride);
+                                      p_in, n_in, p_out, n_out, plan, inv, bin, bout);
     switch (plan.L) {
         TOF_LINE_CASE(32)
         TOF_LINE_CASE(64)
@@ -1703,7 +1691,6 @@ hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int 
     default: break;
     }
 #undef TOF_LINE_CASE
-    if (nsum != 1) return hipErrorInvalidValue;   // partial sums: register lengths only
     const int pitch = plan.L + 1;
     const size_t per_line = 2 * (size_t)pitch * sizeof(cplx<R>);
     int NL = (int)(kLdsBudget / per_line);
@@ -2009,7 +1996,7 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                             int, const FftPlanDev &, cplx<R> *, int);                    \
     template hipError_t launch_line_fft<R>(hipStream_t, const cplx<R> *, cplx<R> *, int, int, long long, \
                                            long long, long long, long long, int, int, int, int,          \
-                                           const FftPlanDev &, bool, BlockMap, BlockMap, int, long long); \
+                                           const FftPlanDev &, bool, BlockMap, BlockMap);                \
     template hipError_t launch_z_pass<R>(hipStream_t, cplx<R> *, int, int, int, int, int, int, int,     \
                                          const SpectrumDev<R> &, const ProductDev &, bool,               \
                                          const FftPlanDev &, BlockMap);                                  \
