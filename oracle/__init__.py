@@ -40,7 +40,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 XX, YY, ZZ, XY, XZ, YZ = range(6)
-J_MEAN_SQ_HZ, J_MEAN_SQ_HZ_GRADXY, J_MEAN_SQ_H_TARGET, J_NEG_HALF_HZ2 = 1, 2, 3, 4
+J_MEAN_SQ_HZ, J_MEAN_SQ_HZ_GRADXY, J_MEAN_SQ_H_TARGET, J_NEG_HALF_HZ2, J_FIELD_GRADIENT = 1, 2, 3, 4, 5
 
 
 def build(force: bool = True) -> str:
@@ -198,14 +198,35 @@ def m0_mask(w) -> int:
 
 
 def objective_box(w):
-    """Cells J reads: the sensor, widened by one cell in x and y for the gradient term."""
+    """Cells J reads: the sensor, widened by one cell in x and y for the
+    gradient term (kind 2), or by the strip and its outer neighbours, two
+    cells, on the -x, +x and -y sides (kind 5)."""
     x0, x1, y0, y1, z0, z1 = w.sensor
+    nx, ny, _ = w.n
     if w.j_kind == J_MEAN_SQ_HZ_GRADXY:
-        nx, ny, _ = w.n
         if x0 < 1 or y0 < 1 or x1 > nx - 1 or y1 > ny - 1:
             raise ValueError("sensor must have in-grid x/y neighbours for the gradient term")
         return (x0 - 1, x1 + 1, y0 - 1, y1 + 1, z0, z1)
+    if w.j_kind == J_FIELD_GRADIENT:
+        if x0 < 2 or y0 < 2 or x1 > nx - 2:
+            raise ValueError("the gradient strip and its outer neighbours must be in the grid")
+        return (x0 - 2, x1 + 2, y0 - 2, y1, z0, z1)
     return tuple(w.sensor)
+
+
+def gradient_strip(w):
+    """The cells of the gradient region of kind 5 with their outward normal:
+    a one-cell strip outside the field region on its -x, +x and -y sides, as
+    (z, y, x, axis, sign) with axis 0 = x, 1 = y."""
+    x0, x1, y0, y1, z0, z1 = w.sensor
+    out = []
+    for z in range(z0, z1):
+        for y in range(y0, y1):
+            out.append((z, y, x0 - 1, 0, -1))
+            out.append((z, y, x1, 0, +1))
+        for x in range(x0, x1):
+            out.append((z, y0 - 1, x, 1, -1))
+    return out
 
 
 def objective_mask(w) -> int:
@@ -250,6 +271,23 @@ def objective(w, H: np.ndarray) -> Tuple[float, np.ndarray]:
         v = hz[z0:z1, y0:y1, x0:x1]
         J = -0.5 * V * float(np.sum(v * v))
         g[2, z0:z1, y0:y1, x0:x1] = -V * v
+    elif w.j_kind == J_FIELD_GRADIENT:
+        # J = -1/2 V [sum_field Hz^2 + beta sum_strip (D_n Hz)^2], D_n the forward
+        # difference along the strip cell's outward normal n: (Hz(s + n) - Hz(s)) / h
+        V = w.h[0] * w.h[1] * w.h[2]
+        beta = w.j_lambda
+        v = hz[z0:z1, y0:y1, x0:x1]
+        total = float(np.sum(v * v))
+        g[2, z0:z1, y0:y1, x0:x1] = -V * v
+        for (z, y, x, axis, sgn) in gradient_strip(w):
+            hstep = w.h[axis]
+            zn, yn, xn = (z, y, x + sgn) if axis == 0 else (z, y + sgn, x)
+            D = (hz[zn, yn, xn] - hz[z, y, x]) / hstep
+            total += beta * D * D
+            c = -V * beta * D / hstep
+            g[2, zn, yn, xn] += c
+            g[2, z, y, x] -= c
+        J = -0.5 * V * total
     else:
         raise ValueError(f"unknown objective kind {w.j_kind}")
     return J, g

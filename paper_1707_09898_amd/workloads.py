@@ -31,6 +31,7 @@ J_MEAN_SQ_HZ = 1          # J = mean_s (Hz_s - t)^2
 J_MEAN_SQ_HZ_GRADXY = 2   # J = mean_s (Hz_s - t)^2 + lam * mean_s (DxHz^2 + DyHz^2)
 J_MEAN_SQ_H_TARGET = 3    # J = mean_s |H_s - H*_s|^2
 J_NEG_HALF_HZ2 = 4        # J = -1/2 V_cell sum_s Hz_s^2   (paper's benchmark objective)
+J_FIELD_GRADIENT = 5      # J = -1/2 V_cell [sum_s Hz_s^2 + beta sum_strip (D_n Hz)^2]  (field and gradient design)
 
 Box = Tuple[int, int, int, int, int, int]  # (x0, x1, y0, y1, z0, z1), half-open
 
@@ -189,7 +190,8 @@ def small_random(seed: int, n=(12, 10, 14), h=(1.0, 1.0, 1.0), design=None, sens
         ht = 0.05 * rng.uniform(-1.0, 1.0, (3,) + sshape)
     return Workload(name=f"small_{seed}", n=n, h=h, design=design, sensor=sensor, p=p,
                     rho=rho, m0=m0, m0_field=m0_field, j_kind=j_kind, j_target=0.2,
-                    j_lambda=0.01 if j_kind == J_MEAN_SQ_HZ_GRADXY else 0.0, h_target=ht)
+                    j_lambda={J_MEAN_SQ_HZ_GRADXY: 0.01, J_FIELD_GRADIENT: 0.5}.get(j_kind, 0.0),
+                    h_target=ht)
 
 
 def by_name(name: str):

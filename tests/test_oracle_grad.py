@@ -38,6 +38,7 @@ def design_cells(w, count, seed):
     lambda: wl.small_random(12, n=(9, 11, 8), h=(0.7, 1.3, 0.9), p=4),
     lambda: wl.small_random(13, n=(8, 8, 10), j_kind=wl.J_MEAN_SQ_H_TARGET, varying_m0=True),
     lambda: wl.small_random(14, n=(10, 9, 8), j_kind=wl.J_NEG_HALF_HZ2, m0=(0.3, -0.4, 0.866)),
+    lambda: wl.small_random(15, n=(12, 11, 8), h=(0.8, 1.1, 1.0), j_kind=wl.J_FIELD_GRADIENT),
 ])
 def test_gradient_matches_central_differences(make):
     w = make()
@@ -125,7 +126,8 @@ def test_objective_gradient_is_exact_derivative():
     """g = dJ/dH checked by central differences of J in H (J is quadratic in
     H, so central differences are exact up to rounding)."""
     rng = np.random.default_rng(4)
-    for kind in (wl.J_MEAN_SQ_HZ, wl.J_MEAN_SQ_HZ_GRADXY, wl.J_MEAN_SQ_H_TARGET, wl.J_NEG_HALF_HZ2):
+    for kind in (wl.J_MEAN_SQ_HZ, wl.J_MEAN_SQ_HZ_GRADXY, wl.J_MEAN_SQ_H_TARGET, wl.J_NEG_HALF_HZ2,
+                 wl.J_FIELD_GRADIENT):
         w = wl.small_random(8, n=(9, 8, 5), j_kind=kind)
         H = rng.normal(size=(3, 5, 8, 9)) * 0.1
         J, g = oracle.objective(w, H)
@@ -136,3 +138,44 @@ def test_objective_gradient_is_exact_derivative():
             Hm[idx] -= 1e-3
             fd = (oracle.objective(w, Hp)[0] - oracle.objective(w, Hm)[0]) / 2e-3
             assert abs(fd - g[idx]) < 1e-10 * max(1.0, abs(g).max())
+
+
+def test_field_gradient_objective_linear_field():
+    """Kind 5 with H_z = a + b x + c y (per cell): the forward differences
+    along the strip's outward normals are exact (-b/dx on the -x side, +b/dx
+    on the +x side, -c/dy on the -y side), so J has a closed form."""
+    w = dataclasses.replace(wl.small_random(3, n=(12, 11, 6), j_kind=wl.J_FIELD_GRADIENT), h=(0.5, 2.0, 1.0))
+    nz, ny, nx = 6, 11, 12
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a, b, c = 0.1, 0.03, -0.02
+    H = np.zeros((3, nz, ny, nx))
+    H[2] = a + b * x + c * y
+    J, g = oracle.objective(w, H)
+    x0, x1, y0, y1, z0, z1 = w.sensor
+    V = 0.5 * 2.0 * 1.0
+    field = H[2, z0:z1, y0:y1, x0:x1]
+    strip = (z1 - z0) * ((y1 - y0) * 2 * (b / 0.5) ** 2 + (x1 - x0) * (c / 2.0) ** 2)
+    want = -0.5 * V * (float(np.sum(field * field)) + w.j_lambda * strip)
+    assert abs(J - want) <= 1e-15 * abs(want)
+
+
+def test_field_gradient_objective_derivative_on_every_cell():
+    """Kind 5: g = dJ/dH_z by central differences at every cell of the
+    objective box (field, strip and the strip's outer neighbours)."""
+    rng = np.random.default_rng(6)
+    w = wl.small_random(9, n=(12, 11, 5), j_kind=wl.J_FIELD_GRADIENT)
+    H = rng.normal(size=(3, 5, 11, 12)) * 0.1
+    J, g = oracle.objective(w, H)
+    x0, x1, y0, y1, z0, z1 = oracle.objective_box(w)
+    nonzero = 0
+    for zz in range(z0, z1):
+        for yy in range(y0, y1):
+            for xx in range(x0, x1):
+                Hp, Hm = H.copy(), H.copy()
+                Hp[2, zz, yy, xx] += 1e-3
+                Hm[2, zz, yy, xx] -= 1e-3
+                fd = (oracle.objective(w, Hp)[0] - oracle.objective(w, Hm)[0]) / 2e-3
+                assert abs(fd - g[2, zz, yy, xx]) < 1e-12 * max(1.0, abs(g).max())
+                nonzero += g[2, zz, yy, xx] != 0
+    # outside the field, the strip and its outer neighbours, J does not depend on H
+    assert np.count_nonzero(g) == nonzero
