@@ -64,8 +64,14 @@ typedef enum {
                                     central differences with the cell sizes; the sensor needs
                                     in-grid x and y neighbours */
     TOF_J_MEAN_SQ_H_TARGET = 3,  /* J = (1/S) sum_s |H_s - H*_s|^2, H* given per sensor cell */
-    TOF_J_NEG_HALF_HZ2 = 4       /* J = -1/2 V_cell sum_s Hz_s^2 (the paper's benchmark objective,
+    TOF_J_NEG_HALF_HZ2 = 4,      /* J = -1/2 V_cell sum_s Hz_s^2 (the paper's benchmark objective,
                                     Sec. "Validation and Benchmarks") */
+    TOF_J_FIELD_GRADIENT = 5     /* J = -1/2 V_cell [sum_s Hz_s^2 + lam sum_q (D_n Hz_q)^2] (the paper's
+                                    field and gradient design): s over the sensor (the field
+                                    region), q over a one-cell strip outside it on its -x, +x and
+                                    -y sides, D_n the forward difference along q's outward
+                                    normal, (Hz(q + n) - Hz(q)) / h_n; the strip and its outer
+                                    neighbours must be in the grid */
 } tof_objective_kind;
 
 /* Grid: the FFT box of nx*ny*nz cells of size dx*dy*dz.  Lx, Ly, Lz are the
@@ -88,7 +94,7 @@ typedef struct {
     int32_t kind;               /* tof_objective_kind */
     tof_box sensor;             /* sensor cells */
     double target;              /* t (kinds 1, 2) */
-    double lambda_grad;         /* lam (kind 2) */
+    double lambda_grad;         /* lam (kinds 2, 5) */
     const double *h_target_host;/* kind 3: H* as [3][sensor cells], C order over the sensor box; else NULL */
 } tof_objective;
 

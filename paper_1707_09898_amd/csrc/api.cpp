@@ -746,7 +746,7 @@ tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj)
 {
     if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
     if (!obj) return fail(ctx, TOF_ERR_INVALID, "objective is null");
-    if (obj->kind < 1 || obj->kind > 4) return fail(ctx, TOF_ERR_INVALID, "unknown objective kind");
+    if (obj->kind < 1 || obj->kind > 5) return fail(ctx, TOF_ERR_INVALID, "unknown objective kind");
     Box sb = to_box(obj->sensor);
     if (!box_ok(sb, ctx->nx, ctx->ny, ctx->nz)) return fail(ctx, TOF_ERR_INVALID, "sensor box outside the grid or empty");
     Box ob = sb;
@@ -754,6 +754,11 @@ tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj)
         if (sb.x0 < 1 || sb.y0 < 1 || sb.x1 > ctx->nx - 1 || sb.y1 > ctx->ny - 1)
             return fail(ctx, TOF_ERR_INVALID, "the gradient term needs in-grid x and y neighbours of the sensor");
         ob = Box{sb.x0 - 1, sb.x1 + 1, sb.y0 - 1, sb.y1 + 1, sb.z0, sb.z1};
+    }
+    if (obj->kind == TOF_J_FIELD_GRADIENT) {
+        if (sb.x0 < 2 || sb.y0 < 2 || sb.x1 > ctx->nx - 2)
+            return fail(ctx, TOF_ERR_INVALID, "the gradient strip and its outer neighbours must be in the grid");
+        ob = Box{sb.x0 - 2, sb.x1 + 2, sb.y0 - 2, sb.y1, sb.z0, sb.z1};
     }
     if (obj->kind == TOF_J_MEAN_SQ_H_TARGET && !obj->h_target_host)
         return fail(ctx, TOF_ERR_INVALID, "kind 3 needs h_target_host");

@@ -435,6 +435,79 @@ __global__ __launch_bounds__(kThreads) void k_zero_outside(R *a, int nx, int ny,
     for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = (R)0;
 }
 
+// dJ/dH_cc at the objective-box cell (x, y, z), and in jterm the cell's term
+// of J's sum (zero off the sensor); the same discrete J as k_objective.  H(x, y)
+// returns component cc of the field at (x, y, z) for any (x, y) of ob.
+template <typename R, typename HF>
+__device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int cc, int x, int y, int z, HF H,
+                                                 double &jterm)
+{
+    const Box &sb = o.sb;
+    const bool in = sb.has(x, y, z);
+    const double invS = 1.0 / (double)o.S;
+    const double h = H(x, y);
+    if (o.kind == 3) {
+        const int s = in ? ((z - sb.z0) * sb.ny() + (y - sb.y0)) * sb.nx() + (x - sb.x0) : 0;
+        const double d = h - o.ht[(long long)cc * o.S + s];
+        jterm = in ? d * d : 0.0;
+        return in ? 2.0 * d * invS : 0.0;
+    }
+    if (o.kind == 4) {
+        jterm = in ? h * h : 0.0;
+        return in ? -o.vcell * h : 0.0;
+    }
+    if (o.kind == 5) {
+        // field region (the sensor): Hz^2; strip cells q outside it on the -x, +x
+        // and -y sides with outward normal n: lam D^2, D = (Hz(q + n) - Hz(q)) / h_n.
+        // dJ/dHz collects -V Hz on the field and the derivative of -1/2 V lam D^2
+        // at q (+V lam D / h_n) and at q + n (-V lam D / h_n).
+        const double V = o.vcell, beta = o.lam;
+        double v = in ? -V * h : 0.0;
+        jterm = in ? h * h : 0.0;
+        const bool zin = z >= sb.z0 && z < sb.z1;
+        const bool yin = zin && y >= sb.y0 && y < sb.y1;
+        const bool xin = zin && x >= sb.x0 && x < sb.x1;
+        const double rdx = 1.0 / o.dx, rdy = 1.0 / o.dy;
+        if (yin && x == sb.x0 - 1) {
+            const double D = (H(x - 1, y) - h) * rdx;
+            jterm += beta * D * D;
+            v += V * beta * D * rdx;
+        }
+        if (yin && x == sb.x0 - 2) v -= V * beta * ((h - H(x + 1, y)) * rdx) * rdx;
+        if (yin && x == sb.x1) {
+            const double D = (H(x + 1, y) - h) * rdx;
+            jterm += beta * D * D;
+            v += V * beta * D * rdx;
+        }
+        if (yin && x == sb.x1 + 1) v -= V * beta * ((h - H(x - 1, y)) * rdx) * rdx;
+        if (xin && y == sb.y0 - 1) {
+            const double D = (H(x, y - 1) - h) * rdy;
+            jterm += beta * D * D;
+            v += V * beta * D * rdy;
+        }
+        if (xin && y == sb.y0 - 2) v -= V * beta * ((h - H(x, y + 1)) * rdy) * rdy;
+        return v;
+    }
+    const double d = h - o.t;
+    double v = in ? 2.0 * d * invS : 0.0;
+    jterm = in ? d * d : 0.0;
+    if (o.kind == 2) {
+        // central differences at this cell (its J term) and at the four sensor
+        // neighbours whose differences read this cell (the transpose); the
+        // divisions by 2 dx, 2 dy as products with their reciprocals
+        const double rx = 0.5 / o.dx, ry = 0.5 / o.dy;
+        const double gx = (H(x + 1, y) - H(x - 1, y)) * rx;
+        const double gy = (H(x, y + 1) - H(x, y - 1)) * ry;
+        if (in) jterm += o.lam * (gx * gx + gy * gy);
+        const double cxs = o.lam * invS / o.dx, cys = o.lam * invS / o.dy;
+        if (sb.has(x - 1, y, z)) v += cxs * ((h - H(x - 2, y)) * rx);
+        if (sb.has(x + 1, y, z)) v -= cxs * ((H(x + 2, y) - h) * rx);
+        if (sb.has(x, y - 1, z)) v += cys * ((h - H(x, y - 2)) * ry);
+        if (sb.has(x, y + 1, z)) v -= cys * ((H(x, y + 2) - h) * ry);
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Objective J(H) in FP64 with a fixed-order reduction (deterministic), and
 // g = dJ/dH (exact derivative of the discrete J) on the whole objective box.
@@ -475,7 +548,26 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
     const int S = sb.nx() * sb.ny() * sb.nz();
     const int nb = gridDim.x;
     double acc = 0.0;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += nb * blockDim.x) {
+    const long long nob = (long long)ob.nx() * ob.ny() * ob.nz();
+    if (kind == 5) {
+        // field and strip terms and dJ/dHz per objective-box cell
+        const ObjectiveDev<R> o{kind, Hs, ob, sb, c_j, nob, S, t, lam, dx, dy, vcell, ht, J, partials, ticket};
+        for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nob;
+             q += (long long)nb * blockDim.x) {
+            const int x = ob.x0 + (int)(q % ob.nx());
+            const int y = ob.y0 + (int)((q / ob.nx()) % ob.ny());
+            const int z = ob.z0 + (int)(q / ((long long)ob.nx() * ob.ny()));
+            auto H = [&](int xx, int yy) -> double {
+                xx = min(max(xx, ob.x0), ob.x1 - 1);
+                yy = min(max(yy, ob.y0), ob.y1 - 1);
+                return hval(Hs, ob, 0, xx, yy, z);
+            };
+            double jt;
+            g[q] = (R)objective_cell(o, 0, x, y, z, H, jt);
+            acc += jt;
+        }
+    }
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; kind != 5 && s < S; s += nb * blockDim.x) {
         const int x = sb.x0 + s % sb.nx();
         const int y = sb.y0 + (s / sb.nx()) % sb.ny();
         const int z = sb.z0 + s / (sb.nx() * sb.ny());
@@ -504,9 +596,8 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
         __syncthreads();
     }
 
-    const long long nob = (long long)ob.nx() * ob.ny() * ob.nz();
     const double invS = 1.0 / (double)S;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < c_j * nob;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; kind != 5 && q < c_j * nob;
          q += (long long)nb * blockDim.x) {
         const int cc = (int)(q / nob);
         const long long w = q % nob;
@@ -552,7 +643,7 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
         if (threadIdx.x == 0) {
             double total = 0.0;
             for (int b = 0; b < nb; ++b) total += sums[b];
-            if (J) *J = (kind == 4) ? -0.5 * vcell * total : total / (double)S;
+            if (J) *J = (kind == 4 || kind == 5) ? -0.5 * vcell * total : total / (double)S;
             *ticket = 0u;
         }
     }
@@ -560,47 +651,6 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
 
 // ---------------------------------------------------------------------------
 // The objective fused with the adjoint's x pass (see launch_objective_xf).
-
-// dJ/dH_cc at the objective-box cell (x, y, z), and in jterm the cell's term
-// of J's sum (zero off the sensor); the same discrete J as k_objective.  H(x, y)
-// returns component cc of the field at (x, y, z) for any (x, y) of ob.
-template <typename R, typename HF>
-__device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int cc, int x, int y, int z, HF H,
-                                                 double &jterm)
-{
-    const Box &sb = o.sb;
-    const bool in = sb.has(x, y, z);
-    const double invS = 1.0 / (double)o.S;
-    const double h = H(x, y);
-    if (o.kind == 3) {
-        const int s = in ? ((z - sb.z0) * sb.ny() + (y - sb.y0)) * sb.nx() + (x - sb.x0) : 0;
-        const double d = h - o.ht[(long long)cc * o.S + s];
-        jterm = in ? d * d : 0.0;
-        return in ? 2.0 * d * invS : 0.0;
-    }
-    if (o.kind == 4) {
-        jterm = in ? h * h : 0.0;
-        return in ? -o.vcell * h : 0.0;
-    }
-    const double d = h - o.t;
-    double v = in ? 2.0 * d * invS : 0.0;
-    jterm = in ? d * d : 0.0;
-    if (o.kind == 2) {
-        // central differences at this cell (its J term) and at the four sensor
-        // neighbours whose differences read this cell (the transpose); the
-        // divisions by 2 dx, 2 dy as products with their reciprocals
-        const double rx = 0.5 / o.dx, ry = 0.5 / o.dy;
-        const double gx = (H(x + 1, y) - H(x - 1, y)) * rx;
-        const double gy = (H(x, y + 1) - H(x, y - 1)) * ry;
-        if (in) jterm += o.lam * (gx * gx + gy * gy);
-        const double cxs = o.lam * invS / o.dx, cys = o.lam * invS / o.dy;
-        if (sb.has(x - 1, y, z)) v += cxs * ((h - H(x - 2, y)) * rx);
-        if (sb.has(x + 1, y, z)) v -= cxs * ((H(x + 2, y) - h) * rx);
-        if (sb.has(x, y - 1, z)) v += cys * ((h - H(x, y - 2)) * ry);
-        if (sb.has(x, y + 1, z)) v -= cys * ((H(x, y + 2) - h) * ry);
-    }
-    return v;
-}
 
 // Block: one row pair (y, y + 1) of ob at one z, one component; NLN lines
 // of P threads.  SPEC false: the field on ob is read from o.Hs.  SPEC true:
@@ -787,7 +837,7 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
         if (tid == 0) {
             double total = 0.0;
             for (int b = 0; b < nb; ++b) total += sums[b];
-            *o.J = o.kind == 4 ? -0.5 * o.vcell * total : total / (double)o.S;
+            *o.J = (o.kind == 4 || o.kind == 5) ? -0.5 * o.vcell * total : total / (double)o.S;
             *o.ticket = 0u;
         }
     }

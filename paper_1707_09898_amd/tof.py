@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtof.so")
 
 TOF_F32, TOF_F64 = 1, 2
-J_MEAN_SQ_HZ, J_MEAN_SQ_HZ_GRADXY, J_MEAN_SQ_H_TARGET, J_NEG_HALF_HZ2 = 1, 2, 3, 4
+J_MEAN_SQ_HZ, J_MEAN_SQ_HZ_GRADXY, J_MEAN_SQ_H_TARGET, J_NEG_HALF_HZ2, J_FIELD_GRADIENT = 1, 2, 3, 4, 5
 
 STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TOF_ERR_OOM",
           -4: "TOF_ERR_HIP", -5: "TOF_ERR_NUMERIC", -6: "TOF_ERR_STATE"}

@@ -59,3 +59,21 @@ def test_short_benchmark_optimization(torch):
     assert r["J_best"] < Js[0] and r["iterations"] >= 5
     assert 0.0 < r["volume_fraction_final"] < 1.0
     assert sum(r["rho_histogram"]["counts"]) == c ** 3
+
+
+@pytest.mark.gpu
+def test_field_gradient_design_start_gradient_matches_oracle(torch):
+    """The field and gradient design at rho = 1 (64 x 64 x 33, field region
+    20 x 20, strip on three sides): J and dJ/drho (FP64) within 1e-10 of the
+    oracle, with the weight that balances the two terms."""
+    from paper_1707_09898_amd import tof
+    beta = ex.balanced_beta(ex.field_gradient_workload())
+    assert beta > 0
+    w = ex.field_gradient_workload(beta)
+    e = tof.engine_for(w, "f64")
+    J, g = e.objective_and_grad(torch.as_tensor(w.rho, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    Jr, gr, _ = oracle.objective_and_grad(w)
+    assert abs(J.item() - Jr) <= 1e-10 * abs(Jr)
+    assert np.abs(g - gr).max() <= 1e-10 * np.abs(gr).max()

@@ -139,6 +139,9 @@ GRAD_CASES = [
     ("sensor3_pow2y", lambda: wl.small_random(37, n=(19, 16, 13), sensor=(6, 12, 5, 11, 10, 13))),
     # varying M0 and a vector target with Ly = 64: three components in and out
     ("vector_pow2y", lambda: wl.small_random(38, n=(12, 32, 10), j_kind=wl.J_MEAN_SQ_H_TARGET, varying_m0=True)),
+    # field and gradient objective (strip on three sides), Lx = Ly = 32, non-cubic cells
+    ("field_gradient", lambda: wl.small_random(39, n=(14, 16, 10), h=(0.8, 1.2, 1.0), j_kind=wl.J_FIELD_GRADIENT)),
+    ("field_gradient_ragged", lambda: wl.small_random(40, n=(13, 11, 9), j_kind=wl.J_FIELD_GRADIENT)),
 ]
 
 
