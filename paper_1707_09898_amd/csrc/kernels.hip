@@ -672,7 +672,6 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
     constexpr int AREA = PITCH > 2 * HX ? PITCH : 2 * HX;   // staging of a row pair's spectra, then the exchange
     constexpr int NT = regfft::twiddle_count(L, E);
     __shared__ cplx<R> lds[NLN * AREA];
-    __shared__ double red[P];
     __shared__ bool last;
     constexpr int TR = 6;   // tile rows: the pair and two more on each side (the stencil's reach)
     __shared__ R tile[TR * L];
@@ -793,13 +792,9 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
             v[m] = cplx<R>{(R)ga, (R)gb};
         }
     }
-    // the block's J terms (all in line slot 0), in a fixed order
-    if (l == 0) red[p] = jsum;
-    __syncthreads();
-    for (int w = P / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
+    // the block's J terms (all in line slot 0, one wave): a butterfly over the
+    // slot's lanes, the same order on every run
+    for (int w = P / 2; w > 0; w >>= 1) jsum += __shfl_xor(jsum, w, P);
     if (l == 0) {
         regfft::fft_line<R, L, E, true>(v, tw, lds, p, false);
 #pragma unroll
@@ -823,7 +818,7 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
     const int nb = gridDim.x * gridDim.y * gridDim.z;
     const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     if (tid == 0) {
-        o.partials[bid] = red[0];
+        o.partials[bid] = jsum;
         __threadfence();
         last = atomicAdd(o.ticket, 1u) == (unsigned int)(nb - 1);
     }
