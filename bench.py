@@ -206,7 +206,8 @@ def main():
     traffic_note = ("FETCH_SIZE + WRITE_SIZE bytes per launch (copy-calibrated), "
                     + os.path.relpath(TRAFFIC_SUMMARY, ROOT)) if traffic is not None and same_src else \
         ("kernel sources changed since the counters were taken" if traffic is not None else
-         "no counter summary for this kernel launch")
+         ("no counter summary for this kernel launch" if os.path.exists(TRAFFIC_SUMMARY) else
+          "counter summary file not found: " + os.path.relpath(TRAFFIC_SUMMARY, ROOT)))
     if not same_src:
         traffic = None
     pass_bytes = sum(by for (_, _, cnt, by) in slots)
