@@ -29,9 +29,40 @@ __device__ __forceinline__ int line_of_thread()
     return l;
 }
 
+// Parity class of the product's tensor components.  With kParRuntime each
+// component's parity is read from prod.comp (or is q itself when all six are
+// used); kParEven fixes at compile time that the single component is a
+// diagonal one (xx, yy or zz: even in x, y and z), so its Kt values are real
+// and need no sign flips.
+constexpr int kParRuntime = -1;
+constexpr int kParEven = 0;
+
+template <int NC, int PAR>
+__device__ __forceinline__ int comp_of(const ProductDev &prod, int q)
+{
+    return NC == 6 ? q : prod.comp[q];
+}
+// odd in z: xz, yz.  These are also the components odd in exactly one of x
+// and y, whose Kt (transformed along x and y) is imaginary.
+template <int NC, int PAR>
+__device__ __forceinline__ bool odd_z(const ProductDev &prod, int q)
+{
+    if constexpr (PAR == kParEven) return false;
+    const int c = comp_of<NC, PAR>(prod, q);
+    return c == 4 || c == 5;
+}
+// odd in y: xy, yz
+template <int NC, int PAR>
+__device__ __forceinline__ bool odd_y(const ProductDev &prod, int q)
+{
+    if constexpr (PAR == kParEven) return false;
+    const int c = comp_of<NC, PAR>(prod, q);
+    return c == 3 || c == 5;
+}
+
 // Kt_q(kx, ky, d) for the product's NC components, with the parity sign of
 // the z offset (xz and yz are odd in z); `d` must satisfy |d| < nzk.
-template <typename R, int NC>
+template <typename R, int NC, int PAR = kParRuntime>
 __device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod, int kx, int ky, int d, R *K)
 {
     const int dq = d < 0 ? -d : d;
@@ -39,32 +70,39 @@ __device__ __forceinline__ void kt_at(const KtDev<R> &kt, const ProductDev &prod
     const long long at = ((long long)kx * kt.nzk + dq) * kt.ky_pitch + ky;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        const int c = NC == 6 ? q : prod.comp[q];
-        const unsigned oz = (c == 4 || c == 5) ? ~0u : 0u;   // xz, yz: odd in z
+        const int c = comp_of<NC, PAR>(prod, q);
         const R v = (NC < 6 || (prod.need >> c & 1)) ? kt.k[c * kt.comp_stride + at] : (R)0;
-        K[q] = flip_sign(v, oz & dsg);
+        K[q] = flip_sign(v, (odd_z<NC, PAR>(prod, q) ? ~0u : 0u) & dsg);
     }
 }
 
 // out_o += sum_i (sum_q W[o][i][q] K_q) x_i; K_q is real, or imaginary
-// (the stored value times i) for the components odd in x (xz, yz).
-template <typename R, int CI, int CO, int NC>
+// (the stored value times i) for the xz and yz components.  A coefficient
+// known to be purely real (or imaginary) scales x without a full complex
+// product.
+template <typename R, int CI, int CO, int NC, int PAR = kParRuntime>
 __device__ __forceinline__ void zsum_mac(const ProductDev &prod, const R *K, const cplx<R> *x, cplx<R> *out)
 {
 #pragma unroll
     for (int o = 0; o < CO; ++o)
 #pragma unroll
         for (int i = 0; i < CI; ++i) {
-            R cre = 0, cim = 0;
+            if constexpr (PAR == kParEven) {
+                static_assert(NC == 1, "a fixed parity class describes a single component");
+                const R w = (R)prod.Wq[o][i][0] * K[0];
+                out[o].x = fma(w, x[i].x, out[o].x);
+                out[o].y = fma(w, x[i].y, out[o].y);
+            } else {
+                R cre = 0, cim = 0;
 #pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                const int c = NC == 6 ? q : prod.comp[q];
-                const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q];
-                const bool im = c == 4 || c == 5;
-                cre += im ? (R)0 : w;
-                cim += im ? w : (R)0;
+                for (int q = 0; q < NC; ++q) {
+                    const R w = (R)(NC == 6 ? prod.W[o][i][q] : prod.Wq[o][i][q]) * K[q];
+                    const bool im = odd_z<NC, PAR>(prod, q);
+                    cre += im ? (R)0 : w;
+                    cim += im ? w : (R)0;
+                }
+                out[o] = cadd(out[o], cmul(cplx<R>{cre, cim}, x[i]));
             }
-            out[o] = cadd(out[o], cmul(cplx<R>{cre, cim}, x[i]));
         }
 }
 

@@ -68,7 +68,8 @@ __device__ __forceinline__ void dft4(cplx<R> &a0, cplx<R> &a1, cplx<R> &a2, cplx
     a3 = csub(t1, t3);
 }
 
-template <typename R>
+// ZIN: v[4..7] are zero (not read), so the first layer reduces to copies.
+template <typename R, bool ZIN = false>
 __device__ __forceinline__ void dft8(cplx<R> *v, bool inv)
 {
     // X[2k] = DFT4(v_n + v_{n+4}), X[2k+1] = DFT4(w8^n (v_n - v_{n+4}))
@@ -76,8 +77,13 @@ __device__ __forceinline__ void dft8(cplx<R> *v, bool inv)
     cplx<R> a[4], b[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        a[n] = cadd(v[n], v[n + 4]);
-        b[n] = csub(v[n], v[n + 4]);
+        if constexpr (ZIN) {
+            a[n] = v[n];
+            b[n] = v[n];
+        } else {
+            a[n] = cadd(v[n], v[n + 4]);
+            b[n] = csub(v[n], v[n + 4]);
+        }
     }
     // w8 = (1 - i)/sqrt2 forward, (1 + i)/sqrt2 inverse
     b[1] = inv ? cplx<R>{(b[1].x - b[1].y) * h, (b[1].x + b[1].y) * h}

@@ -108,12 +108,17 @@ __device__ __forceinline__ void dft16(cplx<R> *v, bool inv)
     }
 }
 
-template <typename R, int RAD>
+// ZIN: the upper half u[RAD/2 ..] is zero (its contents are ignored).
+template <typename R, int RAD, bool ZIN = false>
 __device__ __forceinline__ void dft_pow2(cplx<R> *u, bool inv)
 {
+    if constexpr (ZIN && RAD != 8) {
+#pragma unroll
+        for (int r = RAD / 2; r < RAD; ++r) u[r] = cplx<R>{0, 0};
+    }
     if constexpr (RAD == 2) dft2(u);
     else if constexpr (RAD == 4) dft4(u[0], u[1], u[2], u[3], inv);
-    else if constexpr (RAD == 8) dft8(u, inv);
+    else if constexpr (RAD == 8) dft8<R, ZIN>(u, inv);
     else dft16(u, inv);
 }
 
@@ -140,7 +145,10 @@ __device__ __forceinline__ void load_twiddles(const cplx<R> *table, int p, cplx<
 }
 
 // One stage S of the transform (S = 0 .. num_stages - 1), then the rest.
-template <typename R, int L, int E, int S, bool WAVE>
+// ZIN: the line's upper half (positions L/2 .., slots m >= E/2) is zero on
+// entry; the first stage, whose butterflies take slots m and m + E/2 of the
+// thread, then skips that half.
+template <typename R, int L, int E, int S, bool WAVE, bool ZIN = false>
 __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R> *lds, int p, bool inv)
 {
     constexpr int P = L / E;
@@ -168,7 +176,7 @@ __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R
                     u[r] = cmul(u[r], w);
                 }
             }
-            dft_pow2<R, Rr>(u, inv);
+            dft_pow2<R, Rr, ZIN && S == 0>(u, inv);
             if constexpr (last) {
 #pragma unroll
                 for (int r = 0; r < Rr; ++r) v[b + r * (E / Rr)] = u[r];
@@ -184,7 +192,7 @@ __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R
 #pragma unroll
             for (int m = 0; m < E; ++m) v[m] = lds[swz(p + P * m)];
             exchange_sync<WAVE>();
-            fft_stages<R, L, E, S + 1, WAVE>(v, tw, lds, p, inv);
+            fft_stages<R, L, E, S + 1, WAVE, ZIN>(v, tw, lds, p, inv);
         }
     }
 }
@@ -192,7 +200,7 @@ __device__ __forceinline__ void fft_stages(cplx<R> *v, const cplx<R> *tw, cplx<R
 // NV independent lines at once (line j: v[j][m], exchange area lds + j
 // area): each stage runs for all lines between the same two syncs, which
 // halves the syncs per line and gives the scheduler independent work.
-template <typename R, int L, int E, int S, int NV, bool WAVE>
+template <typename R, int L, int E, int S, int NV, bool WAVE, bool ZIN = false>
 __device__ __forceinline__ void fft_stages_n(cplx<R> (*v)[E], const cplx<R> *tw, cplx<R> *lds, int area, int p,
                                              bool inv)
 {
@@ -222,7 +230,7 @@ __device__ __forceinline__ void fft_stages_n(cplx<R> (*v)[E], const cplx<R> *tw,
                         u[r] = cmul(u[r], w);
                     }
                 }
-                dft_pow2<R, Rr>(u, inv);
+                dft_pow2<R, Rr, ZIN && S == 0>(u, inv);
                 if constexpr (last) {
 #pragma unroll
                     for (int r = 0; r < Rr; ++r) v[j][b + r * (E / Rr)] = u[r];
@@ -241,16 +249,17 @@ __device__ __forceinline__ void fft_stages_n(cplx<R> (*v)[E], const cplx<R> *tw,
 #pragma unroll
                 for (int m = 0; m < E; ++m) v[j][m] = lds[j * area + swz(p + P * m)];
             exchange_sync<WAVE>();
-            fft_stages_n<R, L, E, S + 1, NV, WAVE>(v, tw, lds, area, p, inv);
+            fft_stages_n<R, L, E, S + 1, NV, WAVE, ZIN>(v, tw, lds, area, p, inv);
         }
     }
 }
 
-template <typename R, int L, int E, int NV, bool WAVE = false>
+template <typename R, int L, int E, int NV, bool WAVE = false, bool ZIN = false>
 __device__ __forceinline__ void fft_lines(cplx<R> (*v)[E], const cplx<R> *tw, cplx<R> *lds, int area, int p, bool inv)
 {
     static_assert(!WAVE || 64 % (L / E) == 0, "a wave-synchronized line must lie inside one wave");
-    fft_stages_n<R, L, E, 0, NV, WAVE>(v, tw, lds, area, p, inv);
+    static_assert(!ZIN || stage_radix(L, E, 0) == E, "the zero half is skipped in a first stage of radix E");
+    fft_stages_n<R, L, E, 0, NV, WAVE, ZIN>(v, tw, lds, area, p, inv);
 }
 
 // Transform one line held as v[m] = x[p + P m] by thread p.  `lds` is this
@@ -259,11 +268,14 @@ __device__ __forceinline__ void fft_lines(cplx<R> (*v)[E], const cplx<R> *tw, cp
 // barriers); with WAVE true the line's threads must be P consecutive threads
 // of one wave (see exchange_sync).  On return v[m] holds X[p + P m].
 // Forward: exp(-2 pi i jk/L); inverse: exp(+2 pi i jk/L), unscaled.
-template <typename R, int L, int E, bool WAVE = false>
+// With ZIN the caller asserts that v[m] = 0 for m >= E/2 (the line's upper
+// half); those slots are then not read.
+template <typename R, int L, int E, bool WAVE = false, bool ZIN = false>
 __device__ __forceinline__ void fft_line(cplx<R> *v, const cplx<R> *tw, cplx<R> *lds, int p, bool inv)
 {
     static_assert(!WAVE || 64 % (L / E) == 0, "a wave-synchronized line must lie inside one wave");
-    fft_stages<R, L, E, 0, WAVE>(v, tw, lds, p, inv);
+    static_assert(!ZIN || stage_radix(L, E, 0) == E, "the zero half is skipped in a first stage of radix E");
+    fft_stages<R, L, E, 0, WAVE, ZIN>(v, tw, lds, p, inv);
 }
 
 }  // namespace regfft

@@ -63,18 +63,18 @@ __device__ __forceinline__ void load_line(const cplx<R> *row, int y0, int ny, in
 // kt_half loads the half (slots 0 .. E/2 - 1 and ky = L/2); kt_full completes
 // the line, so the loads of a later row can be issued before the lane
 // exchange of the current one.
-template <typename R, int L, int E, int NC>
+template <typename R, int L, int E, int NC, int PAR>
 __device__ __forceinline__ void kt_half(const KtDev<R> &kt, const ProductDev &prod, int kx, int p, int d,
                                         R (*lo)[NC])
 {
     constexpr int P = L / E;
     constexpr int H = E / 2;
 #pragma unroll
-    for (int m = 0; m < H; ++m) kt_at<R, NC>(kt, prod, kx, p + P * m, d, lo[m]);
-    kt_at<R, NC>(kt, prod, kx, L / 2, d, lo[H]);   // ky = L/2: lane 0's slot H
+    for (int m = 0; m < H; ++m) kt_at<R, NC, PAR>(kt, prod, kx, p + P * m, d, lo[m]);
+    kt_at<R, NC, PAR>(kt, prod, kx, L / 2, d, lo[H]);   // ky = L/2: lane 0's slot H
 }
 
-template <typename R, int L, int E, int NC>
+template <typename R, int L, int E, int NC, int PAR>
 __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (*lo)[NC], R (*K)[NC])
 {
     constexpr int P = L / E;
@@ -90,8 +90,7 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
     for (int m = H; m < E; ++m)
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            const int c = NC == 6 ? q : prod.comp[q];
-            const unsigned oy = (c == 3 || c == 5) ? kSignBit : 0u;
+            const unsigned oy = odd_y<NC, PAR>(prod, q) ? kSignBit : 0u;
             const R mirrored = flip_sign(__shfl(lo[E - 1 - m][q], src), oy);
             // lane 0: ky = P m mirrors to P (E - m), its own slot (m = H is ky = L/2 itself,
             // where the odd components vanish, so no sign is needed)
@@ -103,7 +102,10 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
 // the source box; line slot l transforms rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][nyt]
 // with y from yt0: G copies of the inverse x pass's input, to be added.
-template <typename R, int L, int E, int CI, int CO, int NC, int NR>
+// HALF: the source rows fill exactly the lower half of the line (ys0 = 0,
+// nys = L/2), so the loads need no bounds and the first stage skips the
+// zero half.
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_WAVES_PER_EU))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table)
@@ -112,6 +114,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
     constexpr int NL = kBlock / P;
     constexpr int PITCH = regfft::padded_len(L);
     constexpr int NT = regfft::twiddle_count(L, E);
+    // a line that is a whole wave runs its own trip count; lines sharing a
+    // wave run the same count, a row past the range transforming zeros
+    constexpr bool EXACT = P == 64;
     __shared__ cplx<R> lds[NL * PITCH];
     const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
@@ -127,27 +132,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
         for (int m = 0; m < E; ++m)
 #pragma unroll
             for (int o = 0; o < CO; ++o) acc[r][m][o] = cplx<R>{0, 0};
-    // the same trip count in every slot (a row past the range transforms zeros)
-    const int nit = (rb - ra + NL - 1) / NL;
+    const int nit = EXACT ? (rb - ra > l ? (rb - ra - l + NL - 1) / NL : 0) : (rb - ra + NL - 1) / NL;
     constexpr int H = E / 2;
     for (int it = 0; it < nit; ++it) {
         const int zr = ra + it * NL + l;
-        const int zrc = min(zr, rb - 1);
+        const bool ok = EXACT || zr < rb;
+        const int zrc = EXACT ? zr : min(zr, rb - 1);
         // tensor values (independent of the transform) and the lines, all loads first
         // (fetching the next row ahead instead raises the register count and gains nothing)
         R Kh[NR][H + 1][NC];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            kt_half<R, L, E, NC>(kt, prod, kx, p, zt0 + min(r, nzt - 1) - (zs0 + zrc), Kh[r]);
+            kt_half<R, L, E, NC, PAR>(kt, prod, kx, p, zt0 + min(r, nzt - 1) - (zs0 + zrc), Kh[r]);
         cplx<R> X[CI][E];
 #pragma unroll
-        for (int i = 0; i < CI; ++i)
-            load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + zrc) * nys, ys0, nys, p, zr < rb, X[i]);
+        for (int i = 0; i < CI; ++i) {
+            const cplx<R> *row = A + ((long long)(i * hx + kx) * nzs + zrc) * nys;
+            if constexpr (HALF) {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const cplx<R> a = m < H ? row[p + P * m] : cplx<R>{0, 0};
+                    X[i][m] = ok ? a : cplx<R>{0, 0};
+                }
+            } else {
+                load_line<R, L, E>(row, ys0, nys, p, ok, X[i]);
+            }
+        }
         R K[NR][E][NC];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC>(prod, p, Kh[r], K[r]);
+        for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC, PAR>(prod, p, Kh[r], K[r]);
 #pragma unroll
-        for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E, true>(X[i], tw, my, p, false);
+        for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E, true, HALF>(X[i], tw, my, p, false);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             cplx<R> xm[CI];
@@ -155,14 +170,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
             for (int i = 0; i < CI; ++i) xm[i] = X[i][m];
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                if (r < nzt) zsum_mac<R, CI, CO, NC>(prod, K[r][m], xm, acc[r][m]);
+                if (NR == 1 || r < nzt) zsum_mac<R, CI, CO, NC, PAR>(prod, K[r][m], xm, acc[r][m]);
         }
     }
     // the slots' sums, added in slot order by the first slot, transformed
     // back along y there: the group's partial rows of the target in y space
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        if (r >= nzt) break;
+        if (NR > 1 && r >= nzt) break;
 #pragma unroll
         for (int o = 0; o < CO; ++o) {
             __syncthreads();
@@ -194,7 +209,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
 // the target box; line slot l handles rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys]; C is [CO][hx][nzt][nyt] with y from yt0 (the
 // input layout of the inverse x pass).
-template <typename R, int L, int E, int CI, int CO, int NC, int NR>
+// HALF: the target rows fill exactly the lower half of the line (yt0 = 0,
+// nyt = L/2): the upper half of the inverse transform is never formed.
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_WAVES_PER_EU))) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
                                                           int zt0, int nzt, int rpg, int yt0, int nyt, KtDev<R> kt,
                                                           ProductDev prod, cplx<R> *C, const cplx<R> *table)
@@ -241,7 +258,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
             const int zrc = min(ra + (NV * it + v) * NL + l, rb - 1);
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-                kt_half<R, L, E, NC>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), Kf[v][r]);
+                kt_half<R, L, E, NC, PAR>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), Kf[v][r]);
         }
     };
     fetch(0, Kh);
@@ -250,7 +267,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC>(prod, p, Kh[v][r], K[v][r]);
+            for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC, PAR>(prod, p, Kh[v][r], K[v][r]);
         fetch(it + 1, Kh);   // unconditional: a conditional fetch would be waited for before the transforms
 #pragma unroll
         for (int o = 0; o < CO; ++o) {
@@ -264,11 +281,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
                     for (int oo = 0; oo < CO; ++oo) out[oo] = cplx<R>{0, 0};
 #pragma unroll
                     for (int r = 0; r < NR; ++r) {
-                        if (r >= nzs) break;
+                        if (NR > 1 && r >= nzs) break;
                         cplx<R> xm[CI];
 #pragma unroll
                         for (int i = 0; i < CI; ++i) xm[i] = xs[(r * CI + i) * L + p + P * m];
-                        zsum_mac<R, CI, CO, NC>(prod, K[v][r][m], xm, out);
+                        zsum_mac<R, CI, CO, NC, PAR>(prod, K[v][r][m], xm, out);
                     }
                     Y[v][m] = out[o];
                 }
@@ -281,7 +298,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
 #pragma unroll
                     for (int m = 0; m < E; ++m) {
                         const int n = p + P * m;
-                        if (n >= yt0 && n < yt0 + nyt) dst[n] = Y[v][m];
+                        if (HALF ? m < H : (n >= yt0 && n < yt0 + nyt)) dst[n] = Y[v][m];
                     }
                 }
             }
@@ -302,8 +319,8 @@ constexpr bool scatter_fits(int L, int CI, int NC, int NR, size_t csz)
     return NR * NC <= 6 && scatter_lds(L, CI, NR, csz) <= 96 * 1024;
 }
 
-template <typename R, int L, int CI, int CO, int NC>
-hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
+template <typename R, int L, int CI, int CO, int NC, int PAR, bool HALF>
+hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
                           const ProductDev &prod, const cplx<R> *table, bool check_only)
 {
     constexpr int NRM = kZsumMaxRows;
@@ -314,14 +331,14 @@ hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const
         if (a.nzt == 1) {
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
-                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
                            a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table);
                 return hipGetLastError();
             }
         } else {
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
-                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
                            a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table);
                 return hipGetLastError();
             }
@@ -331,14 +348,14 @@ hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     if (a.nzs == 1) {
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
                                a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table);
             return hipGetLastError();
         }
     } else if (a.nzs <= NRM) {
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM>), grid, dim3(kBlock), 0, st, a.A, a.hx,
+            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
                                a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table);
             return hipGetLastError();
         }
@@ -346,17 +363,33 @@ hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     return hipErrorInvalidValue;
 }
 
+// The many-row side fills exactly the lower half of the y line: the source
+// rows for the gather, the target rows for the scatter.
+template <typename R, int L, int CI, int CO, int NC, int PAR>
+hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
+                          const ProductDev &prod, const cplx<R> *table, bool check_only)
+{
+    const bool gather = a.nzt <= kZsumMaxRows;
+    const bool half = gather ? (a.ys0 == 0 && a.nys == L / 2) : (a.yt0 == 0 && a.nyt == L / 2);
+    if (half) return launch_yzsum_h<R, L, CI, CO, NC, PAR, true>(st, a, rows, kt, prod, table, check_only);
+    return launch_yzsum_h<R, L, CI, CO, NC, PAR, false>(st, a, rows, kt, prod, table, check_only);
+}
+
 template <typename R, int L>
 hipError_t launch_yzsum_c(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
                           const ProductDev &prod, const cplx<R> *table, bool check_only)
 {
     const int key = prod.c_in * 4 + prod.c_out;
-    if (key == 5 && prod.nc == 1) return launch_yzsum_l<R, L, 1, 1, 1>(st, a, rows, kt, prod, table, check_only);
+    if (key == 5 && prod.nc == 1) {
+        if (prod.comp[0] <= 2)   // a diagonal component: real, even in x, y and z
+            return launch_yzsum_l<R, L, 1, 1, 1, kParEven>(st, a, rows, kt, prod, table, check_only);
+        return launch_yzsum_l<R, L, 1, 1, 1, kParRuntime>(st, a, rows, kt, prod, table, check_only);
+    }
     switch (key) {
-    case 5: return launch_yzsum_l<R, L, 1, 1, 6>(st, a, rows, kt, prod, table, check_only);
-    case 7: return launch_yzsum_l<R, L, 1, 3, 6>(st, a, rows, kt, prod, table, check_only);
-    case 13: return launch_yzsum_l<R, L, 3, 1, 6>(st, a, rows, kt, prod, table, check_only);
-    case 15: return launch_yzsum_l<R, L, 3, 3, 6>(st, a, rows, kt, prod, table, check_only);
+    case 5: return launch_yzsum_l<R, L, 1, 1, 6, kParRuntime>(st, a, rows, kt, prod, table, check_only);
+    case 7: return launch_yzsum_l<R, L, 1, 3, 6, kParRuntime>(st, a, rows, kt, prod, table, check_only);
+    case 13: return launch_yzsum_l<R, L, 3, 1, 6, kParRuntime>(st, a, rows, kt, prod, table, check_only);
+    case 15: return launch_yzsum_l<R, L, 3, 3, 6, kParRuntime>(st, a, rows, kt, prod, table, check_only);
     default: return hipErrorInvalidValue;
     }
 }
