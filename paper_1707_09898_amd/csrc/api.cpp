@@ -264,6 +264,7 @@ struct XTail {
     const void *spec = nullptr;
     int nsum = 1;
     long long stride = 0;
+    bool kx_fast = false;   // rows with kx fastest (the fused gather's partials)
 };
 
 template <typename R>
@@ -307,7 +308,7 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
     const double kt_bytes = ncomp * (double)hx * drows * Ly * w;
     if (few && ctx->opt_fuse) {
         // y transforms fused with the direct z sum: no y spectra in HBM
-        YzSumArgs<R> ya{A, B, C, hx, S.y0, S.ny(), S.z0, S.nz(), T.y0, T.ny(), T.z0, T.nz(), 1};
+        YzSumArgs<R> ya{A, B, C, hx, S.y0, S.ny(), S.z0, S.nz(), T.y0, T.ny(), T.z0, T.nz(), 1, tail ? 1 : 0};
         const bool gather = T.nz() <= kZsumMaxRows;
         const int rows = gather ? S.nz() : T.nz();
         // the gather's partial rows must fit in B
@@ -328,7 +329,7 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                     return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
                 }));
                 if (tail) {
-                    *tail = XTail{B, G, part_rows};
+                    *tail = XTail{B, G, part_rows, true};
                     return TOF_OK;
                 }
                 HIP_TRY(ctx, timed(ctx, st, slot0 + 4, part_bytes + x_out, [&] {
@@ -486,6 +487,7 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
                           ctx->sensor.nx() * ctx->sensor.ny() * ctx->sensor.nz(), ctx->target, ctx->lam, ctx->dx,
                           ctx->dy, ctx->dx * ctx->dy * ctx->dz, (const double *)ctx->Ht.p, J,
                           (double *)ctx->partials.p, (unsigned int *)ctx->ticket.p};
+        objective_consts(o);
         const FftPlanDev plx = ctx->px.dev(sizeof(R) == 8);
         cplx<R> *A = (cplx<R> *)ctx->A.p;
         if (launch_objective_xf<R>(st, o, plx, A, ctx->hx, true) == hipSuccess) {
@@ -500,7 +502,7 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
                                   2.0 * sizeof(R) * cj * ctx->hx * ob.nz() * ob.ny();
             HIP_TRY(ctx, timed(ctx, st, 5, fbytes, [&] {
                 return launch_objective_xf<R>(st, o, plx, A, ctx->hx, false, (const cplx<R> *)tail.spec, tail.nsum,
-                                              tail.stride);
+                                              tail.stride, tail.kx_fast);
             }));
             View4<const R> nosrc2{};
             return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true);

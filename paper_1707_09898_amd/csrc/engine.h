@@ -103,12 +103,14 @@ constexpr int kZsumMaxRows = 4;
 template <typename R>
 struct YzSumArgs {
     const cplx<R> *A;        // x-pass output [c_in][hx][nzs][nys]
-    cplx<R> *part;           // gather: partial rows [G][c_out][hx][nzt][nyt] (y space)
+    cplx<R> *part;           // gather: partial rows [G][c_out][hx][nzt][nyt] (y space),
+                             // or [G][c_out][nzt][nyt][hx] with part_kx_fast
     cplx<R> *C;              // scatter: inverse-x input [c_out][hx][nzt][nyt]
     int hx;
     int ys0, nys, zs0, nzs;  // source box rows
     int yt0, nyt, zt0, nzt;  // target box rows
     int rpg;                 // rows per block group: source rows (gather) or target rows (scatter)
+    int part_kx_fast;        // gather: partial rows with kx fastest (for the fused objective)
 };
 
 // Text of the kernel expression last launched by this thread and its work
@@ -186,21 +188,39 @@ struct ObjectiveDev {
     double *J;            // J (one double)
     double *partials;     // kObjMaxBlocks block sums
     unsigned int *ticket; // completion counter, 0 between launches
+    // uniform quotients, formed once per launch (objective_consts)
+    double inv_s;         // 1 / S
+    double rx, ry;        // 1 / (2 dx), 1 / (2 dy)
+    double cxs, cys;      // lam / S / dx, lam / S / dy
+    double rdx, rdy;      // 1 / dx, 1 / dy
 };
+
+template <typename R>
+__host__ __device__ inline void objective_consts(ObjectiveDev<R> &o)
+{
+    o.inv_s = 1.0 / (double)o.S;
+    o.rx = 0.5 / o.dx;
+    o.ry = 0.5 / o.dy;
+    o.cxs = o.lam * o.inv_s / o.dx;
+    o.cys = o.lam * o.inv_s / o.dy;
+    o.rdx = 1.0 / o.dx;
+    o.rdy = 1.0 / o.dy;
+}
 
 // The objective fused with the first pass of the adjoint: per row pair of ob,
 // dJ/dH from the field, the J terms of its sensor cells (block sums added in
 // block order by the last block), and the real-to-complex FFT along x of
 // dJ/dH into A ([c_j][hx][ob.nz][ob.ny], the x-pass layout with source box
 // ob).  The field comes from o.Hs (spec NULL) or, with spec, straight from
-// the forward convolution's inverse x input [c_j][hx][ob.nz][ob.ny] (nsum
-// copies sum_stride apart, added in order), transformed back along x here.
+// the forward convolution's inverse x input [c_j][hx][ob.nz][ob.ny], or the
+// same with kx fastest ([c_j][ob.nz][ob.ny][hx], kx_fast), nsum copies
+// sum_stride apart, added in order, transformed back along x here.
 // Needs a power-of-two Lx in [32, 512] and at most kObjMaxBlocks row pairs,
 // else hipErrorInvalidValue; check_only: report, launch nothing.
 template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
                               bool check_only, const cplx<R> *spec = nullptr, int nsum = 1,
-                              long long sum_stride = 0);
+                              long long sum_stride = 0, bool kx_fast = false);
 
 template <typename R>
 hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,

@@ -444,7 +444,7 @@ __device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int c
 {
     const Box &sb = o.sb;
     const bool in = sb.has(x, y, z);
-    const double invS = 1.0 / (double)o.S;
+    const double invS = o.inv_s;
     const double h = H(x, y);
     if (o.kind == 3) {
         const int s = in ? ((z - sb.z0) * sb.ny() + (y - sb.y0)) * sb.nx() + (x - sb.x0) : 0;
@@ -467,7 +467,7 @@ __device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int c
         const bool zin = z >= sb.z0 && z < sb.z1;
         const bool yin = zin && y >= sb.y0 && y < sb.y1;
         const bool xin = zin && x >= sb.x0 && x < sb.x1;
-        const double rdx = 1.0 / o.dx, rdy = 1.0 / o.dy;
+        const double rdx = o.rdx, rdy = o.rdy;
         if (yin && x == sb.x0 - 1) {
             const double D = (H(x - 1, y) - h) * rdx;
             jterm += beta * D * D;
@@ -495,11 +495,11 @@ __device__ __forceinline__ double objective_cell(const ObjectiveDev<R> &o, int c
         // central differences at this cell (its J term) and at the four sensor
         // neighbours whose differences read this cell (the transpose); the
         // divisions by 2 dx, 2 dy as products with their reciprocals
-        const double rx = 0.5 / o.dx, ry = 0.5 / o.dy;
+        const double rx = o.rx, ry = o.ry;
         const double gx = (H(x + 1, y) - H(x - 1, y)) * rx;
         const double gy = (H(x, y + 1) - H(x, y - 1)) * ry;
         if (in) jterm += o.lam * (gx * gx + gy * gy);
-        const double cxs = o.lam * invS / o.dx, cys = o.lam * invS / o.dy;
+        const double cxs = o.cxs, cys = o.cys;
         if (sb.has(x - 1, y, z)) v += cxs * ((h - H(x - 2, y)) * rx);
         if (sb.has(x + 1, y, z)) v -= cxs * ((H(x + 2, y) - h) * rx);
         if (sb.has(x, y - 1, z)) v += cys * ((h - H(x, y - 2)) * ry);
@@ -551,7 +551,8 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
     const long long nob = (long long)ob.nx() * ob.ny() * ob.nz();
     if (kind == 5) {
         // field and strip terms and dJ/dHz per objective-box cell
-        const ObjectiveDev<R> o{kind, Hs, ob, sb, c_j, nob, S, t, lam, dx, dy, vcell, ht, J, partials, ticket};
+        ObjectiveDev<R> o{kind, Hs, ob, sb, c_j, nob, S, t, lam, dx, dy, vcell, ht, J, partials, ticket};
+        objective_consts(o);
         for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nob;
              q += (long long)nb * blockDim.x) {
             const int x = ob.x0 + (int)(q % ob.nx());
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
 template <typename R, int L, int E, bool SPEC>
 __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
                                                                          const cplx<R> *table, const cplx<R> *spec,
-                                                                         int nsum, long long sum_stride)
+                                                                         int nsum, long long sum_stride, int kxf)
 {
     constexpr int P = L / E;
     constexpr int NLN = SPEC ? 3 : 1;
@@ -704,14 +705,17 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
         cplx<R> *area = lds + l * AREA;
         const int ya = min(ty0 + 2 * l, ty1 - 1), yb = min(ty0 + 2 * l + 1, ty1 - 1);
         const int nyt = ob.ny(), nzt = ob.nz();
-        // the row pair's spectra [h][k] (h = 0: row ya, 1: row yb), copies added in order
+        // the row pair's spectra [h][k] (h = 0: row ya, 1: row yb), copies
+        // added in order; with kx fastest a wave's loads cover whole rows
         constexpr int NIT = (2 * HX + P - 1) / P;
-        const cplx<R> *base = spec + ((long long)cc * hx * nzt + zrel) * nyt;
+        const cplx<R> *base = spec;
         cplx<R> w[NIT];
         auto at = [&](int it) -> long long {
             const int e = min(p + P * it, 2 * HX - 1);
-            const int k = e >> 1;
-            return (long long)k * nzt * nyt + ((e & 1) ? yb : ya) - ob.y0;
+            const int h = e >= HX ? 1 : 0, k = e - h * HX;
+            const int yr = (h ? yb : ya) - ob.y0;
+            return kxf ? ((long long)(cc * nzt + zrel) * nyt + yr) * hx + k
+                       : ((long long)(cc * hx + k) * nzt + zrel) * nyt + yr;
         };
 #pragma unroll
         for (int it = 0; it < NIT; ++it) w[it] = base[at(it)];
@@ -736,7 +740,7 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int e = p + P * it;
-            if (e < 2 * HX) area[(e & 1) * HX + (e >> 1)] = w[it];
+            if (e < 2 * HX) area[e] = w[it];
         }
         regfft::exchange_sync<true>();
         // two real rows in one complex line: Z = X_a + i X_b, X_b from the odd spectrum
@@ -775,27 +779,35 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
         const int row = min(max(y, ty0), ty1 - 1) - ty0;
         return (double)tile[row * L + min(max(x - ob.x0, 0), nx - 1)];
     };
-    // dJ/dH on the pair and the J terms of its sensor cells: line slot 0
-    cplx<R> v[E];
+    // dJ/dH on the pair's cells and their J terms, one cell per thread:
+    // cell e is row ybase + e / nx, column ob.x0 + e % nx
+    __shared__ R gpair[2 * L];
+    __shared__ double jslot[NLN];
     double jsum = 0.0;
+    for (int e = tid; e < 2 * nx; e += NTH) {
+        const int h = e >= nx ? 1 : 0;
+        const int x = ob.x0 + e - h * nx;
+        double jt = 0.0, g = 0.0;
+        if (h == 0 || two) g = objective_cell(o, cc, x, ybase + h, z, H, jt);
+        jsum += jt;
+        gpair[h * L + x] = (R)g;
+    }
+    // the block's J terms: a butterfly over each slot's lanes, then the slots
+    // in order; the same order on every run
+    for (int w = P / 2; w > 0; w >>= 1) jsum += __shfl_xor(jsum, w, P);
+    if (p == 0) jslot[l] = jsum;
+    __syncthreads();
+    if (tid == 0) {
+        for (int s = 1; s < NLN; ++s) jsum += jslot[s];
+    }
     if (l == 0) {
+        cplx<R> v[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int x = p + P * m;
-            double ja = 0.0, jb = 0.0, ga = 0.0, gb = 0.0;
-            if (x >= ob.x0 && x < ob.x1) {
-                ga = objective_cell(o, cc, x, ybase, z, H, ja);
-                if (two) gb = objective_cell(o, cc, x, ybase + 1, z, H, jb);
-            }
-            jsum += ja;
-            jsum += jb;
-            v[m] = cplx<R>{(R)ga, (R)gb};
+            const bool in = x >= ob.x0 && x < ob.x1;
+            v[m] = in ? cplx<R>{gpair[x], gpair[L + x]} : cplx<R>{0, 0};
         }
-    }
-    // the block's J terms (all in line slot 0, one wave): a butterfly over the
-    // slot's lanes, the same order on every run
-    for (int w = P / 2; w > 0; w >>= 1) jsum += __shfl_xor(jsum, w, P);
-    if (l == 0) {
         regfft::fft_line<R, L, E, true>(v, tw, lds, p, false);
 #pragma unroll
         for (int m = 0; m < E; ++m) lds[regfft::swz(p + P * m)] = v[m];
@@ -1637,17 +1649,33 @@ hipError_t allow_lds(K kernel, size_t bytes)
 // ---------------------------------------------------------------------------
 // Launchers
 
-#ifndef TOF_X_NLC512
-#define TOF_X_NLC512 8
+// Complex lines per block (NLC) and lines per thread (LPT) of the register
+// x passes, forward (XF) and inverse (XI), for lengths 256 and 512.  At
+// 256x256x128 the forward pass runs best with two lines a thread, the
+// inverse one (which holds the gradient's accumulators) with one.
+#ifndef TOF_XF_NLC512
+#define TOF_XF_NLC512 8
 #endif
-#ifndef TOF_X_LPT512
-#define TOF_X_LPT512 1
+#ifndef TOF_XF_LPT512
+#define TOF_XF_LPT512 2
 #endif
-#ifndef TOF_X_NLC256
-#define TOF_X_NLC256 8
+#ifndef TOF_XI_NLC512
+#define TOF_XI_NLC512 8
 #endif
-#ifndef TOF_X_LPT256
-#define TOF_X_LPT256 1
+#ifndef TOF_XI_LPT512
+#define TOF_XI_LPT512 1
+#endif
+#ifndef TOF_XF_NLC256
+#define TOF_XF_NLC256 8
+#endif
+#ifndef TOF_XF_LPT256
+#define TOF_XF_LPT256 1
+#endif
+#ifndef TOF_XI_NLC256
+#define TOF_XI_NLC256 8
+#endif
+#ifndef TOF_XI_LPT256
+#define TOF_XI_LPT256 1
 #endif
 
 template <typename R, int L, int NLC, int LPT>
@@ -1676,8 +1704,8 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
     case 32: return launch_xf_reg<R, 32, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
     case 64: return launch_xf_reg<R, 64, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
     case 128: return launch_xf_reg<R, 128, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 256: return launch_xf_reg<R, 256, TOF_X_NLC256, TOF_X_LPT256>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 512: return launch_xf_reg<R, 512, TOF_X_NLC512, TOF_X_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 256: return launch_xf_reg<R, 256, TOF_XF_NLC256, TOF_XF_LPT256>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 512: return launch_xf_reg<R, 512, TOF_XF_NLC512, TOF_XF_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx);
     default: break;
     }
     const int L = plan.L;
@@ -1860,10 +1888,10 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
         case 128:
             return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
         case 256:
-            return launch_xi_reg<R, 256, TOF_X_NLC256, TOF_X_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
+            return launch_xi_reg<R, 256, TOF_XI_NLC256, TOF_XI_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
                                                                     grad, zrows, nsum, sum_stride);
         case 512:
-            return launch_xi_reg<R, 512, TOF_X_NLC512, TOF_X_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
+            return launch_xi_reg<R, 512, TOF_XI_NLC512, TOF_XI_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
                                                                     grad, zrows, nsum, sum_stride);
         default: break;
         }
@@ -1887,7 +1915,7 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
 
 template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
-                              bool check_only, const cplx<R> *spec, int nsum, long long sum_stride)
+                              bool check_only, const cplx<R> *spec, int nsum, long long sum_stride, bool kx_fast)
 {
     const long long nb = (long long)((o.ob.ny() + 1) / 2) * o.ob.nz() * o.c_j;
     if (nb < 1 || nb > kObjMaxBlocks || o.ob.nz() > 65535 || nsum < 1) return hipErrorInvalidValue;
@@ -1899,9 +1927,10 @@ hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const F
         if (check_only) return hipSuccess;                                                                   \
         if (spec)                                                                                            \
             TOF_LAUNCH((k_objective_xf<R, LL, E, true>), grid, dim3(3 * (LL / E)), 0, st, o, A, hx, tw, spec, \
-                       nsum, sum_stride);                                                                    \
+                       nsum, sum_stride, kx_fast ? 1 : 0);                                                   \
         else                                                                                                 \
-            TOF_LAUNCH((k_objective_xf<R, LL, E, false>), grid, dim3(LL / E), 0, st, o, A, hx, tw, spec, 1, 0LL); \
+            TOF_LAUNCH((k_objective_xf<R, LL, E, false>), grid, dim3(LL / E), 0, st, o, A, hx, tw, spec, 1, 0LL, \
+                       0);                                                                                   \
         return hipGetLastError();
     switch (plan.L) {
         TOF_OBJ_CASE(32)
@@ -2049,7 +2078,8 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                             const FftPlanDev &, bool, View4<R>, const DesignDev<R> &,    \
                                             const R *, R *, bool, int, long long);                       \
     template hipError_t launch_objective_xf<R>(hipStream_t, const ObjectiveDev<R> &, const FftPlanDev &,  \
-                                               cplx<R> *, int, bool, const cplx<R> *, int, long long);    \
+                                               cplx<R> *, int, bool, const cplx<R> *, int, long long,     \
+                                               bool);                                                     \
     template hipError_t launch_objective<R>(hipStream_t, int, const R *, Box, Box, int, double, double,  \
                                             double, double, double, const double *, double *, R *,       \
                                             double *, unsigned int *);                                   \

@@ -101,14 +101,15 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
 // Few target rows.  Block (kx, g) takes source rows [g rpg, (g+1) rpg) of
 // the source box; line slot l transforms rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][nyt]
-// with y from yt0: G copies of the inverse x pass's input, to be added.
+// with y from yt0: G copies of the inverse x pass's input, to be added; with
+// kxf [G][CO][nzt][nyt][hx] (rows with kx fastest, for the fused objective).
 // HALF: the source rows fill exactly the lower half of the line (ys0 = 0,
 // nys = L/2), so the loads need no bounds and the first stage skips the
 // zero half.
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_WAVES_PER_EU))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
-    KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table)
+    KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
 {
     constexpr int P = L / E;
     constexpr int NL = kBlock / P;
@@ -194,11 +195,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
                 }
                 // every lane has read its sums before the first exchange write (one wave)
                 regfft::fft_line<R, L, E, true>(v, tw, lds, p, true);
-                cplx<R> *dst = part + (((long long)(blockIdx.y * CO + o) * hx + kx) * nzt + r) * nyt - yt0;
+                // [g][o][kx][r][y], or [g][o][r][y][kx] (kx fastest)
+                const long long gbase = (long long)(blockIdx.y * CO + o) * hx * nzt * nyt;
+                const long long at0 = kxf ? gbase + (long long)r * nyt * hx + kx - (long long)yt0 * hx
+                                          : gbase + ((long long)kx * nzt + r) * nyt - yt0;
+                const long long ys = kxf ? hx : 1;
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int n = p + P * m;
-                    if (n >= yt0 && n < yt0 + nyt) dst[n] = v[m];
+                    if (n >= yt0 && n < yt0 + nyt) part[at0 + n * ys] = v[m];
                 }
             }
         }
@@ -332,14 +337,16 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table);
+                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table,
+                           a.part_kx_fast);
                 return hipGetLastError();
             }
         } else {
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table);
+                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table,
+                           a.part_kx_fast);
                 return hipGetLastError();
             }
         }
