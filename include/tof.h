@@ -188,7 +188,9 @@ tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream);
  * inverse y, inverse x with its epilogue), 5 the objective (with
  * TOF_OPT_FUSE_OBJECTIVE also the adjoint's x pass, slot 6 then unused), 6-10
  * the passes of the adjoint convolution (the last one also zeroes the
- * gradient outside the design region), 11 reserved.  With the fused y /
+ * gradient outside the design region), 11 the sum of the objective's block
+ * terms into J when the fused objective is not followed by the fused
+ * adjoint y / z-sum kernel (which otherwise forms J).  With the fused y /
  * z-sum kernels (TOF_OPT_FUSE_YZ) slot 2 (8 in the adjoint) holds the fused
  * kernel, which also does the inverse y transform, and slots 1 and 3 (7 and
  * 9) are unused.  At most 1024 calls are recorded between reads; later ones

@@ -268,9 +268,11 @@ struct XTail {
 };
 
 template <typename R>
+// jf (if not null and not yet formed): J from the objective's block sums;
+// the fused scatter forms it in its first wave and clears jf->partials.
 tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const DesignDev<R> &dsg,
                     View4<const R> src, Box S, Box T, const ProductDev &prod, bool grad_epi, View4<R> out,
-                    const R *m0u, R *grad, bool a_ready = false, XTail *tail = nullptr)
+                    const R *m0u, R *grad, bool a_ready = false, XTail *tail = nullptr, JFinal *jf = nullptr)
 {
     // the gradient epilogue (T = design box) also zeroes the gradient outside the design box
     const bool zero_rest = grad_epi;
@@ -338,9 +340,11 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                 }));
                 return TOF_OK;
             }
+            if (jf && jf->partials) ya.jf = *jf;
             HIP_TRY(ctx, timed(ctx, st, slot0 + 2, a_elems * cw + kt_half + c_elems * cw, [&] {
                 return launch_yz_sum<R>(st, ya, kt, prod, ply, false);
             }));
+            if (jf) jf->partials = nullptr;
             if (tail) {
                 *tail = XTail{C, 1, 0};
                 return TOF_OK;
@@ -442,14 +446,19 @@ int popcount3(int m) { return (m & 1) + (m >> 1 & 1) + (m >> 2 & 1); }
 
 template <typename R>
 tof_status adjoint_to_grad(tof_ctx *ctx, hipStream_t st, const void *rho, View4<const R> src, Box S,
-                           int comps_mask, void *grad, bool a_ready = false)
+                           int comps_mask, void *grad, bool a_ready = false, JFinal *jf = nullptr)
 {
     DesignDev<R> dsg = design_dev<R>(ctx, rho);
     ProductDev pr = adjoint_product(ctx, comps_mask);
     const R one[3] = {(R)1, (R)0, (R)0};
     View4<R> none{};
     // the last pass also zeroes the gradient outside the design box
-    return convolve<R>(ctx, st, 6, SRC_ARRAY, dsg, src, S, ctx->design, pr, true, none, one, (R *)grad, a_ready);
+    tof_status s = convolve<R>(ctx, st, 6, SRC_ARRAY, dsg, src, S, ctx->design, pr, true, none, one, (R *)grad,
+                               a_ready, nullptr, jf);
+    if (s != TOF_OK || !jf || !jf->partials) return s;
+    // no kernel of the adjoint formed J: a wave of its own does
+    HIP_TRY(ctx, timed(ctx, st, 11, 8.0 * jf->nb + 8.0, [&] { return launch_finalize_j(st, *jf); }));
+    return TOF_OK;
 }
 
 template <typename R>
@@ -505,7 +514,11 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
                                               tail.stride, tail.kx_fast);
             }));
             View4<const R> nosrc2{};
-            return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true);
+            // J from the objective's block sums, formed in the adjoint's first kernel
+            const bool half_vsum = ctx->kind == TOF_J_NEG_HALF_HZ2 || ctx->kind == TOF_J_FIELD_GRADIENT;
+            JFinal jf{(const double *)ctx->partials.p, (int)(((ob.ny() + 1) / 2) * ob.nz() * cj), half_vsum ? 0 : 1,
+                      half_vsum ? -0.5 * o.vcell : (double)o.S, J};
+            return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true, &jf);
         }
     }
     tof_status s = convolve<R>(ctx, st, 0, mode, dsg, nosrc, ctx->design, ob, pf, false, hs, zero3, nullptr);

@@ -106,4 +106,19 @@ __device__ __forceinline__ void zsum_mac(const ProductDev &prod, const R *K, con
         }
 }
 
+// J from the objective's block sums (see JFinal); called by all 64 lanes of
+// one wave.  Lane i holds sum b0 + i; the adds run in block order, the same
+// order as a single thread summing them.
+__device__ __forceinline__ void finalize_j(const JFinal &jf)
+{
+    const int lane = threadIdx.x & 63;
+    double total = 0.0;
+    for (int b0 = 0; b0 < jf.nb; b0 += 64) {
+        const double v = b0 + lane < jf.nb ? jf.partials[b0 + lane] : 0.0;
+        const int n = min(64, jf.nb - b0);
+        for (int i = 0; i < n; ++i) total += __shfl(v, i);
+    }
+    if (lane == 0) *jf.J = jf.div ? total / jf.c : jf.c * total;
+}
+
 }  // namespace tofdev

@@ -100,6 +100,17 @@ struct KtDev {
 constexpr int kZsumMaxRows = 4;
 
 // Arguments of the fused y-transform / z-sum kernels (yzsum.hip).
+// J from the objective's per-block sums, formed by a later kernel of the
+// same evaluation: total = the sums partials[0 .. nb) added in block order,
+// J = c total (div 0) or total / c (div 1).  partials null: nothing to form.
+struct JFinal {
+    const double *partials;
+    int nb;
+    int div;
+    double c;
+    double *J;
+};
+
 template <typename R>
 struct YzSumArgs {
     const cplx<R> *A;        // x-pass output [c_in][hx][nzs][nys]
@@ -111,6 +122,7 @@ struct YzSumArgs {
     int yt0, nyt, zt0, nzt;  // target box rows
     int rpg;                 // rows per block group: source rows (gather) or target rows (scatter)
     int part_kx_fast;        // gather: partial rows with kx fastest (for the fused objective)
+    JFinal jf;               // scatter: J to form first (block (0, 0), one wave), or none
 };
 
 // Text of the kernel expression last launched by this thread and its work
@@ -208,8 +220,9 @@ __host__ __device__ inline void objective_consts(ObjectiveDev<R> &o)
 }
 
 // The objective fused with the first pass of the adjoint: per row pair of ob,
-// dJ/dH from the field, the J terms of its sensor cells (block sums added in
-// block order by the last block), and the real-to-complex FFT along x of
+// dJ/dH from the field, the J terms of its sensor cells (one sum per block
+// into o.partials; the caller forms J from them with a JFinal in a later
+// kernel), and the real-to-complex FFT along x of
 // dJ/dH into A ([c_j][hx][ob.nz][ob.ny], the x-pass layout with source box
 // ob).  The field comes from o.Hs (spec NULL) or, with spec, straight from
 // the forward convolution's inverse x input [c_j][hx][ob.nz][ob.ny], or the
@@ -221,6 +234,10 @@ template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
                               bool check_only, const cplx<R> *spec = nullptr, int nsum = 1,
                               long long sum_stride = 0, bool kx_fast = false);
+
+// One wave forms J from the objective's block sums (when no later kernel of
+// the evaluation does it).
+hipError_t launch_finalize_j(hipStream_t st, const JFinal &jf);
 
 template <typename R>
 hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box sensor, int c_j,

@@ -673,7 +673,6 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
     constexpr int AREA = PITCH > 2 * HX ? PITCH : 2 * HX;   // staging of a row pair's spectra, then the exchange
     constexpr int NT = regfft::twiddle_count(L, E);
     __shared__ cplx<R> lds[NLN * AREA];
-    __shared__ bool last;
     constexpr int TR = 6;   // tile rows: the pair and two more on each side (the stencil's reach)
     __shared__ R tile[TR * L];
     const Box &ob = o.ob;
@@ -717,11 +716,10 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
             return kxf ? ((long long)(cc * nzt + zrel) * nyt + yr) * hx + k
                        : ((long long)(cc * hx + k) * nzt + zrel) * nyt + yr;
         };
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) w[it] = base[at(it)];
-        // up to 8 further copies per round, their loads in flight together
+        // up to 8 copies per round, all their loads in flight together (the
+        // first round holds copy 0, so a few copies cost one memory latency)
         constexpr int GU = 8;
-        for (int g0 = 1; g0 < nsum; g0 += GU) {
+        for (int g0 = 0; g0 < nsum; g0 += GU) {
             cplx<R> u[GU][NIT];
 #pragma unroll
             for (int q = 0; q < GU; ++q) {
@@ -733,9 +731,12 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
                 }
             }
 #pragma unroll
-            for (int q = 0; q < GU; ++q)
+            for (int it = 0; it < NIT; ++it) {
+                cplx<R> acc = g0 == 0 ? u[0][it] : cadd(w[it], u[0][it]);
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) w[it] = cadd(w[it], u[q][it]);
+                for (int q = 1; q < GU; ++q) acc = cadd(acc, u[q][it]);
+                w[it] = acc;
+            }
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -826,29 +827,12 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
         dst[k * kxs + r] = r == 0 ? cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half}
                                   : cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
     }
-    // J: the last block to finish adds the block sums in block order
-    const int nb = gridDim.x * gridDim.y * gridDim.z;
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    if (tid == 0) {
-        o.partials[bid] = jsum;
-        __threadfence();
-        last = atomicAdd(o.ticket, 1u) == (unsigned int)(nb - 1);
-    }
-    __syncthreads();
-    if (last) {
-        // the block sums into LDS by all threads at once, then added in block order
-        __shared__ double sums[kObjMaxBlocks];
-        __threadfence();
-        for (int b = tid; b < nb; b += NTH) sums[b] = o.partials[b];
-        __syncthreads();
-        if (tid == 0) {
-            double total = 0.0;
-            for (int b = 0; b < nb; ++b) total += sums[b];
-            *o.J = (o.kind == 4 || o.kind == 5) ? -0.5 * o.vcell * total : total / (double)o.S;
-            *o.ticket = 0u;
-        }
-    }
+    // the block's J terms; J itself is formed from these by a later kernel
+    if (tid == 0) o.partials[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = jsum;
 }
+
+// One wave: J from the objective's block sums.
+__global__ __launch_bounds__(64) void k_finalize_j(JFinal jf) { finalize_j(jf); }
 
 // ---------------------------------------------------------------------------
 // Projected gradient step on the design box.
@@ -1910,6 +1894,13 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
     e = hipGetLastError();
     if (e != hipSuccess || zrows == 0) return e;
     TOF_LAUNCH(k_zero_outside<R>, dim3(zrows), dim3(kThreads), 0, st, grad, dsg.nx, dsg.ny, dsg.nz, dsg.design);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_j(hipStream_t st, const JFinal &jf)
+{
+    if (!jf.partials || !jf.J || jf.nb < 1) return hipErrorInvalidValue;
+    TOF_LAUNCH(k_finalize_j, dim3(1), dim3(64), 0, st, jf);
     return hipGetLastError();
 }
 

@@ -216,11 +216,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_W
 // input layout of the inverse x pass).
 // HALF: the target rows fill exactly the lower half of the line (yt0 = 0,
 // nyt = L/2): the upper half of the inverse transform is never formed.
+// jf: J formed first by the first wave of block (0, 0) (see JFinal).
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_WAVES_PER_EU))) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
                                                           int zt0, int nzt, int rpg, int yt0, int nyt, KtDev<R> kt,
-                                                          ProductDev prod, cplx<R> *C, const cplx<R> *table)
+                                                          ProductDev prod, cplx<R> *C, const cplx<R> *table,
+                                                          JFinal jf)
 {
+    if (jf.partials && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) finalize_j(jf);
     constexpr int P = L / E;
     constexpr int NL = kBlock / P;
     constexpr int PITCH = regfft::padded_len(L);
@@ -356,14 +359,16 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
             TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table);
+                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table,
+                               a.jf);
             return hipGetLastError();
         }
     } else if (a.nzs <= NRM) {
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
             TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table);
+                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table,
+                               a.jf);
             return hipGetLastError();
         }
     }

@@ -29,7 +29,7 @@ OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE = 1, 2, 3
 
 PROFILE_SLOTS = 12
 PROFILE_NAMES = ["fwd_x", "fwd_y", "fwd_z_product", "fwd_inv_y", "fwd_inv_x_field", "objective",
-                 "adj_x", "adj_y", "adj_z_product", "adj_inv_y", "adj_inv_x_grad", "reserved"]
+                 "adj_x", "adj_y", "adj_z_product", "adj_inv_y", "adj_inv_x_grad", "j_final"]
 
 
 class TofError(RuntimeError):
