@@ -94,10 +94,11 @@ struct tof_ctx {
 namespace {
 
 constexpr int kProfCalls = 1024;
-// Row groups of the fused y / z-sum kernels (blocks = groups x (Lx/2+1)):
-// 8 measured best at 256x256x128 among 4, 7, 8, 15 and 31.
+// Row groups of the fused y / z-sum kernels (blocks = groups x (Lx/2+1)).
+// At 256x256x128 the gather (whose groups the objective kernel adds) runs
+// best with 6 among 4 to 8, the scatter with 8 among 4, 8 and 16.
 #ifndef TOF_YZ_GATHER_GROUPS
-#define TOF_YZ_GATHER_GROUPS 8
+#define TOF_YZ_GATHER_GROUPS 6
 #endif
 #ifndef TOF_YZ_SCATTER_GROUPS
 #define TOF_YZ_SCATTER_GROUPS 8

@@ -20,8 +20,15 @@
 #include "engine.h"
 #include "fft_reg.h"
 
-#ifndef TOF_X_WAVES_PER_EU
-#define TOF_X_WAVES_PER_EU 1
+// Minimum waves per SIMD the compiler must allow (register budget) for the
+// register x passes, forward and inverse (the inverse one with one
+// component and no partial copies; its other forms need more registers);
+// 1 leaves it to the compiler.
+#ifndef TOF_XF_WAVES
+#define TOF_XF_WAVES 1
+#endif
+#ifndef TOF_XI_WAVES
+#define TOF_XI_WAVES 8
 #endif
 #ifndef TOF_ZSUM_U
 #define TOF_ZSUM_U 4
@@ -1296,7 +1303,7 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 // Block: NLC complex lines = 2 NLC source rows of one z (and one component);
 // each thread transforms LPT of them in turn.
 template <typename R, int L, int E, int NLC, int LPT>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_X_WAVES_PER_EU))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
                                                                 Box S, cplx<R> *out, int hx, const cplx<R> *table)
 {
     constexpr int P = L / E;
@@ -1421,7 +1428,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
 // Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
 // each thread transforms LPT lines in turn.
 template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_X_WAVES_PER_EU))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? TOF_XI_WAVES : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
                                                                 View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
                                                                 R m0u2, R *grad, const cplx<R> *table, int zrows,
                                                                 int nsum, long long sum_stride)
