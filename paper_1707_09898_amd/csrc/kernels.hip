@@ -22,13 +22,16 @@
 
 // Minimum waves per SIMD the compiler must allow (register budget) for the
 // register x passes, forward and inverse (the inverse one with one
-// component and no partial copies; its other forms need more registers);
-// 1 leaves it to the compiler.
+// component and no partial copies, FP32 and FP64; its other forms need more
+// registers); 1 leaves it to the compiler.
 #ifndef TOF_XF_WAVES
 #define TOF_XF_WAVES 1
 #endif
 #ifndef TOF_XI_WAVES
 #define TOF_XI_WAVES 8
+#endif
+#ifndef TOF_XI_WAVES_F64
+#define TOF_XI_WAVES_F64 4
 #endif
 #ifndef TOF_ZSUM_U
 #define TOF_ZSUM_U 4
@@ -1428,7 +1431,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
 // Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
 // each thread transforms LPT lines in turn.
 template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? TOF_XI_WAVES : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? (sizeof(R) == 8 ? TOF_XI_WAVES_F64 : TOF_XI_WAVES) : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
                                                                 View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
                                                                 R m0u2, R *grad, const cplx<R> *table, int zrows,
                                                                 int nsum, long long sum_stride)
@@ -1668,6 +1671,19 @@ hipError_t allow_lds(K kernel, size_t bytes)
 #ifndef TOF_XI_LPT256
 #define TOF_XI_LPT256 1
 #endif
+// FP64 at length 512 (twice the LDS and registers per line)
+#ifndef TOF_XF_NLC512_F64
+#define TOF_XF_NLC512_F64 TOF_XF_NLC512
+#endif
+#ifndef TOF_XF_LPT512_F64
+#define TOF_XF_LPT512_F64 TOF_XF_LPT512
+#endif
+#ifndef TOF_XI_NLC512_F64
+#define TOF_XI_NLC512_F64 4
+#endif
+#ifndef TOF_XI_LPT512_F64
+#define TOF_XI_LPT512_F64 TOF_XI_LPT512
+#endif
 
 template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
@@ -1696,7 +1712,12 @@ hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, V
     case 64: return launch_xf_reg<R, 64, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
     case 128: return launch_xf_reg<R, 128, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
     case 256: return launch_xf_reg<R, 256, TOF_XF_NLC256, TOF_XF_LPT256>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 512: return launch_xf_reg<R, 512, TOF_XF_NLC512, TOF_XF_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 512:
+        if constexpr (sizeof(R) == 8)
+            return launch_xf_reg<R, 512, TOF_XF_NLC512_F64, TOF_XF_LPT512_F64>(st, mode, dsg, src, S, c_in, plan, out,
+                                                                             hx);
+        else
+            return launch_xf_reg<R, 512, TOF_XF_NLC512, TOF_XF_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx);
     default: break;
     }
     const int L = plan.L;
@@ -1882,7 +1903,12 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
             return launch_xi_reg<R, 256, TOF_XI_NLC256, TOF_XI_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
                                                                     grad, zrows, nsum, sum_stride);
         case 512:
-            return launch_xi_reg<R, 512, TOF_XI_NLC512, TOF_XI_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
+            if constexpr (sizeof(R) == 8)
+                return launch_xi_reg<R, 512, TOF_XI_NLC512_F64, TOF_XI_LPT512_F64>(st, C, hx, c, T, plan, grad_epilogue,
+                                                                                 out, dsg, m0u, grad, zrows, nsum,
+                                                                                 sum_stride);
+            else
+                return launch_xi_reg<R, 512, TOF_XI_NLC512, TOF_XI_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
                                                                     grad, zrows, nsum, sum_stride);
         default: break;
         }

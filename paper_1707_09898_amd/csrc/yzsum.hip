@@ -30,12 +30,19 @@ namespace {
 using namespace tofdev;
 
 // Minimum waves per SIMD the compiler must allow (register budget) for the
-// gather and the scatter; 1 leaves the register count to the compiler.
+// gather and the scatter, FP32 and FP64; 1 leaves the register count to the
+// compiler.
 #ifndef TOF_YZ_GATHER_WAVES
 #define TOF_YZ_GATHER_WAVES 1
 #endif
 #ifndef TOF_YZ_SCATTER_WAVES
 #define TOF_YZ_SCATTER_WAVES 1
+#endif
+#ifndef TOF_YZ_GATHER_WAVES_F64
+#define TOF_YZ_GATHER_WAVES_F64 3
+#endif
+#ifndef TOF_YZ_SCATTER_WAVES_F64
+#define TOF_YZ_SCATTER_WAVES_F64 1
 #endif
 #ifndef TOF_YZ_ROWS
 #define TOF_YZ_ROWS 1
@@ -112,7 +119,7 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
 // nys = L/2), so the loads need no bounds and the first stage skips the
 // zero half.
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
 {
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_G
 // nyt = L/2): the upper half of the inverse transform is never formed.
 // jf: J formed first by the first wave of block (0, 0) (see JFinal).
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
                                                           int zt0, int nzt, int rpg, int yt0, int nyt, KtDev<R> kt,
                                                           ProductDev prod, cplx<R> *C, const cplx<R> *table,
                                                           JFinal jf)
