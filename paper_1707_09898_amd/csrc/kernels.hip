@@ -1304,11 +1304,14 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 
 // -- pass 1: real-to-complex FFT along x, transposed store ------------------
 // Block: NLC complex lines = 2 NLC source rows of one z (and one component);
-// each thread transforms LPT of them in turn.
-template <typename R, int L, int E, int NLC, int LPT>
+// each thread transforms LPT of them in turn.  HALF (design sources only):
+// the design rows fill exactly the lower half of the line (x in [0, L/2)),
+// so the upper half is neither loaded nor transformed in the first stage.
+template <typename R, int L, int E, int NLC, int LPT, bool HALF>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
                                                                 Box S, cplx<R> *out, int hx, const cplx<R> *table)
 {
+    constexpr int ME = HALF ? E / 2 : E;   // slots that can hold data
     constexpr int P = L / E;
     constexpr int TY = 2 * NLC;
     constexpr int PITCH = regfft::padded_len(L);
@@ -1331,7 +1334,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
         // row-level facts once; per element only the x range remains
         const int yA = ybase + r0, yB = yA + 1;
         const bool okA = r0 < nrow, okB = r0 + 1 < nrow;
-        if (mode == SRC_ARRAY) {
+        if (!HALF && mode == SRC_ARRAY) {
             const R *rowZ = src.ptr + c * src.cs + (long long)(z - src.oz) * src.zs - src.ox;
             const R *rowA = rowZ + (long long)((okA ? yA : ybase) - src.oy) * src.ys;
             const R *rowB = rowZ + (long long)((okB ? yB : ybase) - src.oy) * src.ys;
@@ -1356,45 +1359,48 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
             const long long offB = ((long long)z * dsg.ny + (okB ? yB : ybase)) * dsg.nx;
             const R *rhoA = dsg.rho + offA, *rhoB = dsg.rho + offB;
             const int xl = max(S.x0, dsg.design.x0), xh = min(S.x1, dsg.design.x1);
-            // every load from an address clamped into the row, all issued
-            // before the arithmetic; out-of-range elements are selected away
-            R ra[E], rb[E], fa[E], fb[E];
+            // every load from an address clamped into the row (with HALF all
+            // in it), all issued before the arithmetic; out-of-range
+            // elements are selected away
+            auto col = [&](int m) { return HALF ? p + P * m : min(p + P * m, dsg.nx - 1); };
+            R ra[ME], rb[ME], fa[ME], fb[ME];
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int xc = min(p + P * m, dsg.nx - 1);
-                ra[m] = rhoA[xc];
-                rb[m] = rhoB[xc];
+            for (int m = 0; m < ME; ++m) {
+                ra[m] = rhoA[col(m)];
+                rb[m] = rhoB[col(m)];
                 fa[m] = fb[m] = (R)1;
             }
             if (mode == SRC_RHO_VECTOR) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int xc = min(p + P * m, dsg.nx - 1);
-                    fa[m] = dsg.m0f[c * ncell + offA + xc];
-                    fb[m] = dsg.m0f[c * ncell + offB + xc];
+                for (int m = 0; m < ME; ++m) {
+                    fa[m] = dsg.m0f[c * ncell + offA + col(m)];
+                    fb[m] = dsg.m0f[c * ncell + offB + col(m)];
                 }
             }
             if (dsg.mask) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int xc = min(p + P * m, dsg.nx - 1);
-                    if (!dsg.mask[offA + xc]) fa[m] = 0;
-                    if (!dsg.mask[offB + xc]) fb[m] = 0;
+                for (int m = 0; m < ME; ++m) {
+                    if (!dsg.mask[offA + col(m)]) fa[m] = 0;
+                    if (!dsg.mask[offB + col(m)]) fb[m] = 0;
                 }
             }
-            ipow_n<R, E>(ra, dsg.p);
-            ipow_n<R, E>(rb, dsg.p);
+            ipow_n<R, ME>(ra, dsg.p);
+            ipow_n<R, ME>(rb, dsg.p);
 #pragma unroll
             for (int m = 0; m < E; ++m) {
+                if (m >= ME) {
+                    v[m] = cplx<R>{0, 0};
+                    continue;
+                }
                 const int x = p + P * m;
-                const bool in = x >= xl && x < xh;
+                const bool in = HALF || (x >= xl && x < xh);
                 const R a = (in && inA) ? ra[m] * fa[m] : (R)0;
                 const R b = (in && inB) ? rb[m] * fb[m] : (R)0;
                 v[m] = cplx<R>{a, b};
             }
         }
         cplx<R> *my = lds + l * PITCH;
-        regfft::fft_line<R, L, E, true>(v, tw, my, p, false);
+        regfft::fft_line<R, L, E, true, HALF>(v, tw, my, p, false);
         // natural-order spectrum of the line into LDS (its own slot)
 #pragma unroll
         for (int m = 0; m < E; ++m) my[regfft::swz(p + P * m)] = v[m];
@@ -1429,8 +1435,9 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
 
 // -- pass 5: complex-to-real inverse FFT along x + epilogue -----------------
 // Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
-// each thread transforms LPT lines in turn.
-template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS>
+// each thread transforms LPT lines in turn.  HALF: every column the pass
+// stores lies in the lower half of the line (x < L/2).
+template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? (sizeof(R) == 8 ? TOF_XI_WAVES_F64 : TOF_XI_WAVES) : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
                                                                 View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
                                                                 R m0u2, R *grad, const cplx<R> *table, int zrows,
@@ -1448,6 +1455,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
         }
         return;
     }
+    constexpr int ME = HALF ? E / 2 : E;   // output slots that can be stored
     constexpr int P = L / E;
     constexpr int TY = 2 * NLC;
     constexpr int PITCH = regfft::padded_len(L);
@@ -1553,7 +1561,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
             const int l = l0 + j * (NLC / LPT);
             if (!grad_epi) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     const int x = p + P * m;
                     if (x < T.x0 || x >= T.x1) continue;
 #pragma unroll
@@ -1567,7 +1575,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
                 }
             } else if (dsg.m0f) {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     // columns past nx accumulate a clamped value and are never stored
                     const int xc = min(p + P * m, dsg.nx - 1);
 #pragma unroll
@@ -1579,7 +1587,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
                 }
             } else {
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     acc[j][0][m] += m0u[cc] * v[j][m].x;
                     acc[j][1][m] += m0u[cc] * v[j][m].y;
                 }
@@ -1601,20 +1609,20 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
                 const long long off = ((long long)z * dsg.ny + y) * dsg.nx;
                 const R *rho = dsg.rho + off;
                 R *gr = grad + off;
-                R rv[E];
-                bool mk[E];
+                R rv[ME];
+                bool mk[ME];
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     rv[m] = rho[min(p + P * m, dsg.nx - 1)];
                     mk[m] = true;
                 }
                 if (dsg.mask) {
 #pragma unroll
-                    for (int m = 0; m < E; ++m) mk[m] = dsg.mask[off + min(p + P * m, dsg.nx - 1)] != 0;
+                    for (int m = 0; m < ME; ++m) mk[m] = dsg.mask[off + min(p + P * m, dsg.nx - 1)] != 0;
                 }
-                ipow_n<R, E>(rv, dsg.p - 1);
+                ipow_n<R, ME>(rv, dsg.p - 1);
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = 0; m < ME; ++m) {
                     const int x = p + P * m;
                     if (x >= dsg.nx) continue;
                     R g = 0;
@@ -1685,22 +1693,34 @@ hipError_t allow_lds(K kernel, size_t bytes)
 #define TOF_XI_LPT512_F64 TOF_XI_LPT512
 #endif
 
-template <typename R, int L, int NLC, int LPT>
-hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
-                         const FftPlanDev &plan, cplx<R> *out, int hx)
+template <typename R, int L, int NLC, int LPT, bool HALF>
+hipError_t launch_xf_reg_h(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
+                           const FftPlanDev &plan, cplx<R> *out, int hx)
 {
     constexpr int E = 8;
     if ((long long)((S.ny() + 2 * NLC - 1) / (2 * NLC)) * S.nz() * c_in < 512) {
         // few rows: one row pair per block
         dim3 grid((S.ny() + 1) / 2, S.nz(), c_in);
-        TOF_LAUNCH((k_xf_reg<R, L, E, 1, 1>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
+        TOF_LAUNCH((k_xf_reg<R, L, E, 1, 1, HALF>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
                            (const cplx<R> *)plan.tw);
         return hipGetLastError();
     }
     dim3 grid((S.ny() + 2 * NLC - 1) / (2 * NLC), S.nz(), c_in);
-    TOF_LAUNCH((k_xf_reg<R, L, E, NLC, LPT>), grid, dim3((NLC / LPT) * (L / E)), 0, st, mode, dsg, src, S,
+    TOF_LAUNCH((k_xf_reg<R, L, E, NLC, LPT, HALF>), grid, dim3((NLC / LPT) * (L / E)), 0, st, mode, dsg, src, S,
                        out, hx, (const cplx<R> *)plan.tw);
     return hipGetLastError();
+}
+
+// Design sources whose rows fill exactly x in [0, L/2) take the HALF form.
+template <typename R, int L, int NLC, int LPT>
+hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
+                         const FftPlanDev &plan, cplx<R> *out, int hx)
+{
+    const int xl = S.x0 > dsg.design.x0 ? S.x0 : dsg.design.x0;
+    const int xh = S.x1 < dsg.design.x1 ? S.x1 : dsg.design.x1;
+    const bool half = mode != SRC_ARRAY && xl == 0 && xh == L / 2 && dsg.nx == L / 2;
+    if (half) return launch_xf_reg_h<R, L, NLC, LPT, true>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    return launch_xf_reg_h<R, L, NLC, LPT, false>(st, mode, dsg, src, S, c_in, plan, out, hx);
 }
 
 template <typename R>
@@ -1871,14 +1891,23 @@ hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
     const int gz = (int)((zrows + (long long)gx * kZeroRowsPerBlock - 1) / ((long long)gx * kZeroRowsPerBlock));
     dim3 grid(gx, T.nz() + gz);
     dim3 block((NLC / LPT) * (L / E));
-#define TOF_XI_LAUNCH(CC, PSV)                                                                                   \
-    TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, CC, PSV>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out, dsg, \
-               m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows, nsum, sum_stride)
-    if (c == 1 && nsum == 1) TOF_XI_LAUNCH(1, false);
-    else if (c == 1) TOF_XI_LAUNCH(1, true);
-    else if (c == 3 && nsum == 1) TOF_XI_LAUNCH(3, false);
-    else if (c == 3) TOF_XI_LAUNCH(3, true);
+    // every stored column in the lower half of the line: the upper half of
+    // the last stage and of the epilogue is never formed
+    const bool half = T.x1 <= L / 2 && (!grad_epilogue || dsg.nx <= L / 2);
+#define TOF_XI_LAUNCH(CC, PSV, HV)                                                                               \
+    TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, CC, PSV, HV>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out, \
+               dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows, nsum, sum_stride)
+#define TOF_XI_LAUNCH_H(CC, PSV)                  \
+    do {                                          \
+        if (half) TOF_XI_LAUNCH(CC, PSV, true);   \
+        else TOF_XI_LAUNCH(CC, PSV, false);       \
+    } while (0)
+    if (c == 1 && nsum == 1) TOF_XI_LAUNCH_H(1, false);
+    else if (c == 1) TOF_XI_LAUNCH_H(1, true);
+    else if (c == 3 && nsum == 1) TOF_XI_LAUNCH_H(3, false);
+    else if (c == 3) TOF_XI_LAUNCH_H(3, true);
     else return hipErrorInvalidValue;
+#undef TOF_XI_LAUNCH_H
 #undef TOF_XI_LAUNCH
     return hipGetLastError();
 }
