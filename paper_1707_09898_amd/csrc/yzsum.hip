@@ -39,7 +39,7 @@ using namespace tofdev;
 #define TOF_YZ_SCATTER_WAVES 1
 #endif
 #ifndef TOF_YZ_GATHER_WAVES_F64
-#define TOF_YZ_GATHER_WAVES_F64 3
+#define TOF_YZ_GATHER_WAVES_F64 1
 #endif
 #ifndef TOF_YZ_SCATTER_WAVES_F64
 #define TOF_YZ_SCATTER_WAVES_F64 1
