@@ -8,14 +8,16 @@
 //   gather  (few target rows): per kx, the y FFT of every source row times
 //           Kt, summed over the source rows of a group and transformed back
 //           along y; each group writes its partial target rows in y space,
-//           and the inverse x pass adds the partials (in group order) while
-//           staging.  (Adding them in the last block of each kx instead
-//           needs a device-scope release per block, an L2 write-back on this
-//           chip, which costs far more.)
+//           and the next kernel (the inverse x pass, or the fused objective,
+//           for which the rows are stored with kx fastest) adds the partials
+//           in group order while staging.  (Adding them in the last block of
+//           each kx instead needs a device-scope release per block, an L2
+//           write-back on this chip, which costs far more.)
 //   scatter (few source rows): per kx, the y FFT of the source rows (kept in
 //           LDS), then for every target row the sum against Kt and the
 //           inverse y FFT, written straight into the layout of the inverse x
-//           pass.
+//           pass.  Its first wave can also form J from the objective's
+//           block sums (JFinal).
 //
 // A y line is held by P = L / E threads (thread p: positions p + P m, see
 // fft_reg.h); a 256-thread block runs NL = 256 / P lines side by side.
