@@ -11,6 +11,11 @@ the counters were taken.
 
   python -m paper_1707_09898_amd.rocprof_summary --trace T.csv [--fetch F.csv --write W.csv
          --copy-mib N] --command "..." --title "..." --out profiles/NAME.md
+
+With --sq S.csv (a pass of SQ_WAVES and SQ_INSTS_* counters) it writes
+instead the instruction summary: VALU, LDS and vector-memory instructions
+per wave and the VALU issue time over the chip next to each kernel's
+duration.
 """
 from __future__ import annotations
 
@@ -139,6 +144,49 @@ def summarize(args):
         fo.write("\n".join(lines))
 
 
+# VALU issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles;
+# 256 CUs x 4 SIMDs at 2.4 GHz
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+CYCLES_PER_WAVE_INSTR = 4
+
+
+def summarize_sq(args):
+    """Per kernel launch shape: waves, VALU / LDS / vector-memory instructions
+    per wave (SQ counters), and the time the VALU instructions alone take to
+    issue over the whole chip, next to the mean duration from the trace."""
+    trace = read_trace(args.trace)
+    cnt = {c: read_counter(args.sq, c) for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS",
+                                                  "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")}
+    lines = [f"# {args.title}", "", "Commands (from the repository root; rocprofv3 run from /tmp):", ""]
+    lines += [f"    {c}" for c in args.command]
+    lines += ["", f"HIP source hash: `{source_hash()}` (paper_1707_09898_amd/csrc).", "",
+              f"VALU issue time = VALU instructions x {CYCLES_PER_WAVE_INSTR} cycles / ({SIMDS} SIMDs x "
+              f"{CLOCK_HZ / 1e9:.1f} GHz): the kernel's duration if VALU issue were its only limit.", "",
+              "| kernel | type | work items | waves | VALU/wave | LDS/wave | VMEM rd+wr/wave | VALU issue us | mean us | issue / mean |",
+              "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = []
+    for key, waves_l in cnt["SQ_WAVES"].items():
+        base, ty, items = key
+        if not base.startswith("k_") or key not in trace:
+            continue
+        avg = lambda c: sum(cnt[c][key]) / len(cnt[c][key]) if key in cnt[c] else 0.0
+        waves = avg("SQ_WAVES")
+        if waves <= 0:
+            continue
+        valu = avg("SQ_INSTS_VALU")
+        issue_us = valu * CYCLES_PER_WAVE_INSTR / (SIMDS * CLOCK_HZ) * 1e6
+        mean_us = sum(trace[key]) / len(trace[key])
+        rows.append((mean_us, f"| {base} | {ty} | {items} | {waves:.0f} | {valu / waves:.0f} | "
+                              f"{avg('SQ_INSTS_LDS') / waves:.0f} | "
+                              f"{(avg('SQ_INSTS_VMEM_RD') + avg('SQ_INSTS_VMEM_WR')) / waves:.0f} | "
+                              f"{issue_us:.2f} | {mean_us:.2f} | {issue_us / mean_us:.2f} |"))
+    lines += [r for _, r in sorted(rows, key=lambda t: -t[0])]
+    lines.append("")
+    with open(args.out, "w") as fo:
+        fo.write("\n".join(lines))
+
+
 def lookup(summary_path, base, ty, items):
     """(fetch + write bytes per launch, hash matches the sources) from a
     summary, or (None, False) when the summary or the kernel is not there."""
@@ -163,5 +211,7 @@ if __name__ == "__main__":
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--title", default="rocprofv3 summary")
+    ap.add_argument("--sq", help="counter CSV of an SQ_WAVES / SQ_INSTS_* pass: write the VALU summary")
     ap.add_argument("--out", required=True)
-    summarize(ap.parse_args())
+    a = ap.parse_args()
+    summarize_sq(a) if a.sq else summarize(a)
