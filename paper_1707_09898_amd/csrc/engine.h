@@ -224,11 +224,11 @@ __host__ __device__ inline void objective_consts(ObjectiveDev<R> &o)
 // into o.partials; the caller forms J from them with a JFinal in a later
 // kernel), and the real-to-complex FFT along x of
 // dJ/dH into A ([c_j][hx][ob.nz][ob.ny], the x-pass layout with source box
-// ob).  The field comes from o.Hs (spec NULL) or, with spec, straight from
-// the forward convolution's inverse x input [c_j][hx][ob.nz][ob.ny], or the
-// same with kx fastest ([c_j][ob.nz][ob.ny][hx], kx_fast), nsum copies
-// sum_stride apart, added in order, transformed back along x here.
-// Needs a power-of-two Lx in [32, 512] and at most kObjMaxBlocks row pairs,
+// ob).  The field comes straight from the forward convolution's inverse x
+// input `spec` [c_j][hx][ob.nz][ob.ny], or the same with kx fastest
+// ([c_j][ob.nz][ob.ny][hx], kx_fast), nsum copies sum_stride apart, added in
+// order, transformed back along x here.  Needs a power-of-two Lx in
+// [32, 512], at most kObjMaxBlocks row pairs and (unless check_only) spec,
 // else hipErrorInvalidValue; check_only: report, launch nothing.
 template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,

@@ -663,20 +663,19 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
 // ---------------------------------------------------------------------------
 // The objective fused with the adjoint's x pass (see launch_objective_xf).
 
-// Block: one row pair (y, y + 1) of ob at one z, one component; NLN lines
-// of P threads.  SPEC false: the field on ob is read from o.Hs.  SPEC true:
-// the field rows the pair needs (with the stencil's reach) come straight
-// from the forward convolution: line slot l transforms rows ty0 + 2l,
-// ty0 + 2l + 1 back along x from their kx spectra spec[g][cc][kx][zrel][y]
-// (nsum copies sum_stride apart, added in order), so the field is never
-// stored.
-template <typename R, int L, int E, bool SPEC>
-__global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
-                                                                         const cplx<R> *table, const cplx<R> *spec,
-                                                                         int nsum, long long sum_stride, int kxf)
+// Block: one row pair (y, y + 1) of ob at one z, one component; NLN = 3
+// lines of P threads.  The field rows the pair needs (with the stencil's
+// reach) come straight from the forward convolution: line slot l transforms
+// rows ty0 + 2l, ty0 + 2l + 1 back along x from their kx spectra (nsum
+// copies sum_stride apart, added in order; [cc][kx][zrel][y], or with kxf
+// [cc][zrel][y][kx]), so the field is never stored.
+template <typename R, int L, int E>
+__global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
+                                                            const cplx<R> *table, const cplx<R> *spec, int nsum,
+                                                            long long sum_stride, int kxf)
 {
     constexpr int P = L / E;
-    constexpr int NLN = SPEC ? 3 : 1;
+    constexpr int NLN = 3;
     constexpr int NTH = NLN * P;
     constexpr int HX = L / 2 + 1;
     constexpr int PITCH = regfft::padded_len(L);
@@ -698,19 +697,7 @@ __global__ __launch_bounds__((SPEC ? 3 : 1) * (L / E)) void k_objective_xf(Objec
     regfft::load_twiddles<R, L, E>(table, p, tw);
     // component cc of the field on rows ty0 .. ty1-1 of this z into LDS
     const int ty0 = max(ob.y0, ybase - 2), ty1 = min(ob.y1, ybase + 4), nx = ob.nx();
-    if constexpr (!SPEC) {
-        // all loads first (addresses clamped into ob)
-        const R *plane = o.Hs + cc * o.nob + (long long)zrel * ob.ny() * nx;
-        R hv[TR * E];
-#pragma unroll
-        for (int it = 0; it < TR * E; ++it) {
-            const int e = p + P * it;
-            const int row = e / L, col = e % L;
-            hv[it] = plane[(long long)(min(ty0 + row, ty1 - 1) - ob.y0) * nx + min(col, nx - 1)];
-        }
-#pragma unroll
-        for (int it = 0; it < TR * E; ++it) tile[p + P * it] = hv[it];
-    } else {
+    {
         cplx<R> *area = lds + l * AREA;
         const int ya = min(ty0 + 2 * l, ty1 - 1), yb = min(ty0 + 2 * l + 1, ty1 - 1);
         const int nyt = ob.ny(), nzt = ob.nz();
@@ -1972,18 +1959,15 @@ hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const F
 {
     const long long nb = (long long)((o.ob.ny() + 1) / 2) * o.ob.nz() * o.c_j;
     if (nb < 1 || nb > kObjMaxBlocks || o.ob.nz() > 65535 || nsum < 1) return hipErrorInvalidValue;
+    if (!check_only && !spec) return hipErrorInvalidValue;
     constexpr int E = 8;
     const dim3 grid((o.ob.ny() + 1) / 2, o.ob.nz(), o.c_j);
     const cplx<R> *tw = (const cplx<R> *)plan.tw;
 #define TOF_OBJ_CASE(LL)                                                                                     \
     case LL:                                                                                                 \
         if (check_only) return hipSuccess;                                                                   \
-        if (spec)                                                                                            \
-            TOF_LAUNCH((k_objective_xf<R, LL, E, true>), grid, dim3(3 * (LL / E)), 0, st, o, A, hx, tw, spec, \
-                       nsum, sum_stride, kx_fast ? 1 : 0);                                                   \
-        else                                                                                                 \
-            TOF_LAUNCH((k_objective_xf<R, LL, E, false>), grid, dim3(LL / E), 0, st, o, A, hx, tw, spec, 1, 0LL, \
-                       0);                                                                                   \
+        TOF_LAUNCH((k_objective_xf<R, LL, E>), grid, dim3(3 * (LL / E)), 0, st, o, A, hx, tw, spec, nsum,     \
+                   sum_stride, kx_fast ? 1 : 0);                                                             \
         return hipGetLastError();
     switch (plan.L) {
         TOF_OBJ_CASE(32)
