@@ -515,11 +515,13 @@ tof_status run_objective_and_grad(tof_ctx *ctx, hipStream_t st, const void *rho,
                                               tail.stride, tail.kx_fast);
             }));
             View4<const R> nosrc2{};
-            // J from the objective's block sums, formed in the adjoint's first kernel
+            // J from the objective's block sums, formed by the adjoint's fused
+            // scatter (its first kernel) or a kernel of its own; nothing when
+            // the caller passes no J
             const bool half_vsum = ctx->kind == TOF_J_NEG_HALF_HZ2 || ctx->kind == TOF_J_FIELD_GRADIENT;
             JFinal jf{(const double *)ctx->partials.p, (int)(((ob.ny() + 1) / 2) * ob.nz() * cj), half_vsum ? 0 : 1,
                       half_vsum ? -0.5 * o.vcell : (double)o.S, J};
-            return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true, &jf);
+            return adjoint_to_grad<R>(ctx, st, rho, nosrc2, ob, jmask, grad, true, J ? &jf : nullptr);
         }
     }
     tof_status s = convolve<R>(ctx, st, 0, mode, dsg, nosrc, ctx->design, ob, pf, false, hs, zero3, nullptr);

@@ -9,6 +9,8 @@ FP32, the accuracy targets of the gradient engine; J relative to |J|.
 import dataclasses
 import sys
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -169,6 +171,24 @@ def test_gpu_objective_and_grad_match_oracle(torch, name, make, dtype, path):
     # zero outside the design region
     chi = oracle.box_mask(w.n, w.design)
     assert np.all(g[chi == 0] == 0.0)
+
+
+@pytest.mark.parametrize("path", list(GRAD_PATHS))
+def test_gpu_objective_and_grad_without_J(torch, path):
+    """J is optional at the boundary: with a NULL J the gradient is the same,
+    bit for bit, on every path (nothing forms or writes J)."""
+    t = tof()
+    w = wl.small_random(43, n=(16, 16, 9))
+    say("grad without J", path, w.n)
+    e = engine_on_path(w, "f32", path)
+    rho = dev(torch, w.rho, e.dtype)
+    J, g_ref = e.objective_and_grad(rho)
+    g = torch.full_like(g_ref, float("nan"))
+    st = t.lib().tof_objective_and_grad(e._ctx, ctypes.c_void_p(rho.data_ptr()), None,
+                                        ctypes.c_void_p(g.data_ptr()), None)
+    torch.cuda.synchronize()
+    assert st == 0, t.lib().tof_last_error(e._ctx)
+    assert torch.equal(g, g_ref)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
