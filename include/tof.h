@@ -228,9 +228,12 @@ const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_i
  *                    the many-row side never go through device memory.
  *   TOF_OPT_FUSE_OBJECTIVE  tof_objective_and_grad evaluates J and dJ/dH in
  *                    the kernel that starts the adjoint (its FFT along x;
- *                    power-of-two Lx from 32 to 512), so dJ/dH is never
- *                    stored.  The J reduction order differs from the
- *                    separate objective kernel's (rounding only).
+ *                    power-of-two Lx from 32 to 512), which also transforms
+ *                    the field rows it reads back along x, so neither the
+ *                    field nor dJ/dH is stored; the per-block J terms are
+ *                    added, in block order, by the adjoint's next kernel.
+ *                    The J reduction order differs from the separate
+ *                    objective kernel's (rounding only).
  * Errors: TOF_ERR_INVALID.
  */
 #define TOF_OPT_ZSUM 1
