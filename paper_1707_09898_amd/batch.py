@@ -4,8 +4,9 @@ as one HIP graph.
 Every design keeps its density, gradient and J resident on the device.  The
 gradient evaluations are recorded once into a graph (torch.cuda.CUDAGraph
 over the library's own launches): the designs are spread over several
-streams forked from the capture stream, so independent designs overlap on
-the GPU, and one replay evaluates the whole batch.  Each context owns its
+streams forked from the capture stream (balanced by padded volume), so
+independent designs overlap on the GPU, and one replay evaluates the whole
+batch.  Each context owns its
 workspaces, so concurrent designs share nothing.
 """
 from __future__ import annotations
@@ -32,7 +33,24 @@ class DesignBatch:
             self.grad.append(torch.empty_like(r))
             self.J.append(torch.empty(1, dtype=torch.float64, device="cuda"))
         self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
+        self.assignment = self._balance(len(self.streams))
         self.graph = None
+
+    def _balance(self, nstreams: int) -> List[List[int]]:
+        """Designs per stream: largest first, each to the stream with the least
+        work so far (work ~ padded volume), so that the streams end together."""
+        cost = []
+        for e in self.engines:
+            Lx, Ly, Lz = e.padded_lengths()
+            cost.append(Lx * Ly * Lz)
+        order = sorted(range(len(self.engines)), key=lambda i: -cost[i])
+        load = [0] * nstreams
+        out: List[List[int]] = [[] for _ in range(nstreams)]
+        for i in order:
+            k = min(range(nstreams), key=lambda s: load[s])
+            out[k].append(i)
+            load[k] += cost[i]
+        return out
 
     def __len__(self):
         return len(self.engines)
@@ -41,9 +59,9 @@ class DesignBatch:
         """Fork the side streams from `root`, enqueue every design, join back."""
         for s in self.streams:
             s.wait_stream(root)
-        for i, e in enumerate(self.engines):
-            s = self.streams[i % len(self.streams)]
-            e.objective_and_grad(self.rho[i], self.grad[i], self.J[i], stream=s)
+        for s, designs in zip(self.streams, self.assignment):
+            for i in designs:
+                self.engines[i].objective_and_grad(self.rho[i], self.grad[i], self.J[i], stream=s)
         for s in self.streams:
             root.wait_stream(s)
 
