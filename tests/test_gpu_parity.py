@@ -205,6 +205,34 @@ def test_gpu_adjoint_vjp_matches_oracle(torch, dtype):
     assert rel_inf(grad, ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gpu_c2_hundred_evaluations(torch, dtype):
+    """Configuration 2 as specified: 100 gradient evaluations of the
+    64 x 64 x 64 problem.  Every J equals the first bit for bit (fixed-order
+    reductions), so does the last gradient, and both match the oracle."""
+    w = wl.config2()
+    e = tof().engine_for(w, dtype)
+    rho = dev(torch, w.rho, e.dtype)
+    J0, g0 = e.objective_and_grad(rho)
+    g = torch.empty_like(g0)
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    Js = torch.empty(100, dtype=torch.float64, device="cuda")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for k in range(100):
+        e.objective_and_grad(rho, g, J)
+        Js[k:k + 1].copy_(J)
+    t1.record()
+    torch.cuda.synchronize()
+    say(f"c2 {dtype}: 100 evaluations, {t0.elapsed_time(t1) / 100:.4f} ms each (with the J copies)")
+    assert torch.all(Js == J0)
+    assert torch.equal(g, g0)
+    Jr, gr, _ = cached(("grad", "c2"), lambda: oracle.objective_and_grad(w))
+    assert abs(float(J0.item()) - Jr) <= TOL[dtype] * abs(Jr)
+    assert rel_inf(host(g), gr) <= TOL[dtype]
+
+
 def test_gpu_is_deterministic_and_stream_safe(torch):
     w = wl.config2()
     e = tof().engine_for(w, "f32")
