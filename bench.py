@@ -75,17 +75,20 @@ def cpu_baseline(w, layers=16):
 
 
 def batch_measurement(torch, wl, args):
-    """64 independent designs of uneven size (FP32), padded lengths chosen by
-    the autotuner, one graph replay per batch evaluation."""
+    """64 independent designs of uneven size (FP32), schedules (padded
+    lengths and pass structure) chosen by the autotuner, one graph replay per
+    batch evaluation."""
     from paper_1707_09898_amd import autotune
     from paper_1707_09898_amd.batch import DesignBatch
     ws = wl.config5()
     t0 = time.perf_counter()
-    lengths = None
+    lengths = passes = None
     if not args.no_autotune:
-        lengths = [autotune.tune(w, "f32", evals=2)[0] for w in ws]
+        sched = [autotune.tune_schedule(w, "f32", evals=2)[0] for w in ws]
+        lengths = [L for L, _ in sched]
+        passes = [name for _, name in sched]
     t1 = time.perf_counter()
-    b = DesignBatch(ws, "f32", lengths, streams=args.batch_streams)
+    b = DesignBatch(ws, "f32", lengths, streams=args.batch_streams, passes=passes)
     nbytes = b.algorithmic_bytes()
     b.capture()
     for _ in range(3):
@@ -113,7 +116,8 @@ def batch_measurement(torch, wl, args):
            "ms_per_batch_eager": ms_eager, "bytes_per_batch": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
            "streams": args.batch_streams, "autotuned": not args.no_autotune,
            "autotune_s": round(t1 - t0, 1),
-           "lengths": [list(map(int, e.padded_lengths())) for e in b.engines]}
+           "lengths": [list(map(int, e.padded_lengths())) for e in b.engines],
+           "passes": passes}
     b.close()
     print(f"[bench] c5 batch: {ms:.3f} ms per 64 designs ({res['evals_per_s']:.0f} evals/s), eager {ms_eager:.3f} ms",
           file=sys.stderr, flush=True)

@@ -1,12 +1,15 @@
-"""Padded-length autotuner.
+"""Schedule autotuner: padded lengths and pass structure.
 
 Any padded length L >= 2n - 1 gives the same (exact) convolution, so the
 length per axis is a free schedule choice: the default is the smallest even
 7-smooth L >= 2n (mixed-radix LDS transforms for non-powers of two), while a
 power of two in [32, 512] selects the register-resident transforms and, for
 the y axis, the fused y / z-sum kernels, at the price of a longer line.  The
-tuner times one gradient evaluation per candidate triple on the GPU and keeps
-the fastest; results are cached per (grid, cell, objective) key.
+pass structure is free too (the same convolution up to rounding order):
+the fused y / z-sum kernels, the direct z sum in a pass of its own, or FFTs
+along z.  tune() times gradient evaluations per candidate length triple,
+tune_schedule() per (triple, pass structure) pair, on the GPU, and keeps the
+fastest; results are cached per (grid, cell, objective) key.
 """
 from __future__ import annotations
 
@@ -57,7 +60,11 @@ def candidate_triples(n: Sequence[int]) -> List[Tuple[int, int, int]]:
     return out
 
 
+# pass structures: (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ, TOF_OPT_FUSE_OBJECTIVE)
+PASSES = {"fused": (1, 1, 1), "zsum": (1, 0, 1), "zfft": (0, 0, 1)}
+
 _CACHE: Dict[tuple, Tuple[int, int, int]] = {}
+_SCHED: Dict[tuple, Tuple[Tuple[int, int, int], str]] = {}
 
 
 def key_of(w, dtype: str) -> tuple:
@@ -95,3 +102,45 @@ def tune(w, dtype: str = "f32", evals: int = 3, candidates=None) -> Tuple[Tuple[
 def cached(w, dtype: str = "f32"):
     """The tuned lengths of a workload if tune() has seen it, else None."""
     return _CACHE.get(key_of(w, dtype))
+
+
+def apply_passes(e, name: str):
+    """Set the pass structure `name` (a key of PASSES) on engine e."""
+    from . import tof
+    zsum, fuse, fobj = PASSES[name]
+    e.set_option(tof.OPT_ZSUM, zsum)
+    e.set_option(tof.OPT_FUSE_YZ, fuse)
+    e.set_option(tof.OPT_FUSE_OBJECTIVE, fobj)
+
+
+def tune_schedule(w, dtype: str = "f32", evals: int = 3, candidates=None, passes=None):
+    """Time `evals` gradient evaluations for every (length triple, pass
+    structure) pair of workload w; returns ((triple, pass name),
+    {(triple, pass name): ms per evaluation})."""
+    import torch
+    from . import tof
+    key = key_of(w, dtype)
+    cands = candidate_triples(w.n) if candidates is None else list(candidates)
+    names = list(PASSES) if passes is None else list(passes)
+    times = {}
+    for L in cands:
+        e = tof.engine_for(w, dtype, L=L)
+        rho = torch.as_tensor(w.rho, dtype=e.dtype, device="cuda")
+        grad = torch.empty_like(rho)
+        J = torch.empty(1, dtype=torch.float64, device="cuda")
+        for name in names:
+            apply_passes(e, name)
+            e.objective_and_grad(rho, grad, J)   # warm-up
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(evals):
+                e.objective_and_grad(rho, grad, J)
+            t1.record()
+            torch.cuda.synchronize()
+            times[(tuple(L), name)] = t0.elapsed_time(t1) / evals
+        e.close()
+    best = min(times, key=times.get)
+    _SCHED[key] = best
+    _CACHE[key] = best[0]
+    return best, times

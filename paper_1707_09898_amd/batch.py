@@ -16,9 +16,9 @@ from typing import List, Optional, Sequence
 
 class DesignBatch:
     def __init__(self, workloads: Sequence, dtype: str = "f32", lengths: Optional[Sequence] = None,
-                 streams: int = 4):
+                 streams: int = 4, passes: Optional[Sequence[str]] = None):
         import torch
-        from . import tof
+        from . import autotune, tof
         self.torch = torch
         self.workloads = list(workloads)
         self.dtype = dtype
@@ -27,6 +27,8 @@ class DesignBatch:
         for i, w in enumerate(self.workloads):
             L = None if lengths is None else lengths[i]
             e = tof.engine_for(w, dtype, L=L)
+            if passes is not None:
+                autotune.apply_passes(e, passes[i])
             self.engines.append(e)
             r = torch.as_tensor(w.rho, dtype=e.dtype, device="cuda")
             self.rho.append(r)

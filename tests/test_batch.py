@@ -130,3 +130,32 @@ def test_tuned_lengths_give_the_same_result(torch):
     for J, g in res[1:]:
         assert abs(J - J0) <= 1e-12 * abs(J0)
         assert np.abs(g - g0).max() <= 1e-12 * np.abs(g0).max()
+
+
+@pytest.mark.gpu
+def test_tuned_schedules_give_the_same_result(torch):
+    """The schedule tuner times every (length triple, pass structure) pair,
+    returns one of them, and a batch built from tuned schedules matches the
+    same designs evaluated one by one with the library's defaults."""
+    from paper_1707_09898_amd import tof
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = smallest_designs(3)
+    sched = []
+    for w in ws:
+        best, times = autotune.tune_schedule(w, "f64", evals=1)
+        say("schedule", w.n, best)
+        assert best in times
+        assert len(times) == len(autotune.candidate_triples(w.n)) * len(autotune.PASSES)
+        sched.append(best)
+    b = DesignBatch(ws, "f64", [L for L, _ in sched], streams=2, passes=[p for _, p in sched])
+    b.run_eager()
+    got = b.results()
+    b.close()
+    for w, (J, g) in zip(ws, got):
+        e = tof.engine_for(w, "f64")
+        J0, g0 = e.objective_and_grad(torch.as_tensor(w.rho, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        g0 = g0.cpu().numpy()
+        e.close()
+        assert abs(J - J0.item()) <= 1e-12 * abs(J0.item())
+        assert np.abs(g - g0).max() <= 1e-12 * np.abs(g0).max()
