@@ -173,6 +173,7 @@ def main():
             e.objective_and_grad(rho, grad, J)
         ms = time_steps(torch, e, rho, grad, J, steps)
         J_main = float(J.item())
+        grad_main = grad.double()   # the timed path's gradient, for the precision report
         # per-launch timing in a second pass over the same number of steps
         e.profile(True)
         for _ in range(args.profile_steps):
@@ -195,6 +196,7 @@ def main():
         results[dtype] = {"ms": ms, "prof": prof, "kernels": kernels, "L": L, "J": J_main, "paths": paths}
         print(f"[bench] {dtype}: {ms:.4f} ms/eval, {1000.0 / ms:.1f} evals/s, J={J_main:.10e}",
               file=sys.stderr, flush=True)
+        results[dtype]["grad"] = grad_main
         e.close()
         del rho, grad
 
@@ -236,6 +238,12 @@ def main():
         "f64_plain": {"value": 1000.0 / results["f64"]["ms"], "ms_per_step": results["f64"]["ms"],
                       "steps": args.f64_steps},
         "speedup_f32_over_f64": results["f64"]["ms"] / r32["ms"],
+        # FP32 against the plain FP64 path on the same input (the FP64 path
+        # itself is pinned to the oracle at 1e-10 by the parity tests)
+        "precision_f32_vs_f64": {
+            "J_rel": abs(r32["J"] - results["f64"]["J"]) / abs(results["f64"]["J"]),
+            "grad_rel_inf": float((r32["grad"] - results["f64"]["grad"]).abs().max() /
+                                  results["f64"]["grad"].abs().max())},
         "bytes_per_eval": {"passes": pass_bytes, "full_field_model": model},
         "effective_GBps": {"passes": pass_bytes * evals / 1e9, "full_field_model": model * evals / 1e9},
         "per_kernel_us": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)][0]}": round(avg * 1e3, 2)
