@@ -720,18 +720,23 @@ __global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o,
             cplx<R> u[GU][NIT];
 #pragma unroll
             for (int q = 0; q < GU; ++q) {
-                const cplx<R> *bg = base + min(g0 + q, nsum - 1) * sum_stride;
+                // copies past nsum issue no loads (a wave keeps at most 63
+                // loads in flight: more would cost a second memory latency)
+                if (g0 + q < nsum) {
+                    const cplx<R> *bg = base + (g0 + q) * sum_stride;
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const cplx<R> a = bg[at(it)];
-                    u[q][it] = g0 + q < nsum ? a : cplx<R>{0, 0};
+                    for (int it = 0; it < NIT; ++it) u[q][it] = bg[at(it)];
+                } else {
+#pragma unroll
+                    for (int it = 0; it < NIT; ++it) u[q][it] = cplx<R>{0, 0};
                 }
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 cplx<R> acc = g0 == 0 ? u[0][it] : cadd(w[it], u[0][it]);
 #pragma unroll
-                for (int q = 1; q < GU; ++q) acc = cadd(acc, u[q][it]);
+                for (int q = 1; q < GU; ++q)
+                    if (g0 + q < nsum) acc = cadd(acc, u[q][it]);
                 w[it] = acc;
             }
         }
