@@ -1500,11 +1500,14 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
             cplx<R> w[GU][NIT];
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
-                const cplx<R> *sg = src + min(g0 + u, nsum - 1) * sum_stride;
+                // copies past nsum issue no loads (at most 63 in flight a wave)
+                if (g0 + u < nsum) {
+                    const cplx<R> *sg = src + (g0 + u) * sum_stride;
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const cplx<R> a = sg[min(it, itmax) * sstep];
-                    w[u][it] = g0 + u < nsum ? a : cplx<R>{0, 0};
+                    for (int it = 0; it < NIT; ++it) w[u][it] = sg[min(it, itmax) * sstep];
+                } else {
+#pragma unroll
+                    for (int it = 0; it < NIT; ++it) w[u][it] = cplx<R>{0, 0};
                 }
             }
 #pragma unroll
@@ -1513,7 +1516,8 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
                 if (k < HX && r < nrow) {
                     cplx<R> acc = lds[r * HX + k];
 #pragma unroll
-                    for (int u = 0; u < GU; ++u) acc = cadd(acc, w[u][it]);
+                    for (int u = 0; u < GU; ++u)
+                        if (g0 + u < nsum) acc = cadd(acc, w[u][it]);
                     lds[r * HX + k] = acc;
                 }
             }

@@ -56,10 +56,13 @@ def host(t):
 # the objective in its own kernel, FFTs along z
 # (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ, TOF_OPT_FUSE_OBJECTIVE)
 PATHS = {"fused": (1, 1, 1), "zsum": (1, 0, 0), "zfft": (0, 0, 0)}
-# the gradient also with the objective fused but the y / z passes not: the
+# the gradient also with the objective fused but the y / z passes not (the
 # adjoint then ends without the fused scatter, and a kernel of its own forms
-# J from the objective's block sums
-GRAD_PATHS = dict(PATHS, objective_only=(1, 0, 1))
+# J from the objective's block sums)
+GRAD_PATHS = dict(PATHS, objective_only=(1, 0, 1),
+                  # and the y / z passes fused but not the objective: the
+                  # inverse x pass then adds the gather's partial copies
+                  fused_yz_only=(1, 1, 0))
 
 
 def engine_on_path(w, dtype, path):
