@@ -14,6 +14,19 @@ from __future__ import annotations
 from typing import List, Optional, Sequence
 
 
+def balance(cost: Sequence[float], nstreams: int) -> List[List[int]]:
+    """Indices per stream: largest cost first, each to the stream with the
+    least cost so far, so that the streams end at about the same time."""
+    order = sorted(range(len(cost)), key=lambda i: -cost[i])
+    load = [0.0] * nstreams
+    out: List[List[int]] = [[] for _ in range(nstreams)]
+    for i in order:
+        k = min(range(nstreams), key=lambda s: load[s])
+        out[k].append(i)
+        load[k] += cost[i]
+    return out
+
+
 class DesignBatch:
     def __init__(self, workloads: Sequence, dtype: str = "f32", lengths: Optional[Sequence] = None,
                  streams: int = 4, passes: Optional[Sequence[str]] = None):
@@ -39,20 +52,12 @@ class DesignBatch:
         self.graph = None
 
     def _balance(self, nstreams: int) -> List[List[int]]:
-        """Designs per stream: largest first, each to the stream with the least
-        work so far (work ~ padded volume), so that the streams end together."""
+        """Designs per stream, balanced by padded volume (see balance)."""
         cost = []
         for e in self.engines:
             Lx, Ly, Lz = e.padded_lengths()
             cost.append(Lx * Ly * Lz)
-        order = sorted(range(len(self.engines)), key=lambda i: -cost[i])
-        load = [0] * nstreams
-        out: List[List[int]] = [[] for _ in range(nstreams)]
-        for i in order:
-            k = min(range(nstreams), key=lambda s: load[s])
-            out[k].append(i)
-            load[k] += cost[i]
-        return out
+        return balance(cost, nstreams)
 
     def __len__(self):
         return len(self.engines)

@@ -49,6 +49,21 @@ def test_candidate_lengths_are_valid(n):
         assert cands[1] & (cands[1] - 1) == 0
 
 
+def test_balance_assigns_every_design_once_and_evens_the_streams():
+    from paper_1707_09898_amd.batch import balance
+    rng = np.random.default_rng(7)
+    cost = [float(v) for v in rng.integers(1, 1000, size=64)]
+    for ns in (1, 2, 4, 8):
+        out = balance(cost, ns)
+        assert len(out) == ns
+        assert sorted(i for s in out for i in s) == list(range(len(cost)))
+        loads = [sum(cost[i] for i in s) for s in out]
+        # largest-first greedy: no stream exceeds the mean by more than the largest cost
+        assert max(loads) <= sum(cost) / ns + max(cost)
+        for s in out:   # each stream runs its designs largest first
+            assert all(cost[a] >= cost[b] for a, b in zip(s, s[1:]))
+
+
 def test_candidate_triples_start_with_the_default():
     t = autotune.candidate_triples((37, 64, 33))
     assert t[0] == (80, 128, 70) and (128, 128, 128) in t and len(set(t)) == len(t)
