@@ -10,7 +10,8 @@ Where each step comes from (paper sections and equations):
 
 * ``magnetization``  M = chi rho^p M0 (Sec. "Methodology", the penalized
   magnetization M(rho) = rho^p M0; chi is the design region's characteristic
-  function, as in the benchmark section).
+  function, as in the benchmark section: an index box, optionally intersected
+  with a cell mask, ``design_chi``).
 * ``newell_table``   the discrete demagnetization tensor, eq. (demag_tensor),
   in quad precision (C, ``oracle.c``).
 * ``field``          the discrete convolution, eq. (convolution), as a direct
@@ -23,6 +24,12 @@ Where each step comes from (paper sections and equations):
   operator as the forward one (N symmetric and even).  The paper prints this
   with a leading minus sign; differentiating the discrete J directly gives a
   plus sign, and the finite-difference tests pin the plus sign.
+* ``project_step``   one step of the bound-constrained update that keeps
+  0 <= rho <= 1 (Sec. Methodology relaxes rho to [0, 1]; Sec. Discretization
+  minimizes with a quasi-Newton method that handles that bound).  The measured
+  loop uses the simplest such method, a projected gradient step normalized by
+  the largest gradient magnitude on the design cells; its definition is
+  written out here.
 
 Parity pins are in ``tests/test_oracle_*.py``.
 """
@@ -169,6 +176,15 @@ def box_mask(n, box) -> np.ndarray:
     return chi
 
 
+def design_chi(w) -> np.ndarray:
+    """chi of the design region: 1 on the cells of the design box whose mask
+    entry (if the workload has a mask) is nonzero, 0 elsewhere."""
+    chi = box_mask(w.n, w.design)
+    if getattr(w, "mask", None) is not None:
+        chi = chi * (np.asarray(w.mask) != 0)
+    return chi
+
+
 def ipow(x: np.ndarray, p: int) -> np.ndarray:
     """x^p for integer p >= 0 by repeated multiplication."""
     r = np.ones_like(x)
@@ -187,7 +203,7 @@ def m0_array(w) -> np.ndarray:
 def magnetization(w, rho: Optional[np.ndarray] = None) -> np.ndarray:
     """M = chi rho^p M0 (Sec. Methodology), [3][nz][ny][nx]."""
     rho = w.rho if rho is None else rho
-    chi = box_mask(w.n, w.design)
+    chi = design_chi(w)
     return (chi * ipow(rho, w.p))[None] * m0_array(w)
 
 
@@ -310,7 +326,7 @@ def adjoint_field(w, g: np.ndarray, table: Optional[np.ndarray] = None) -> np.nd
 def gradient_from_adjoint(w, A: np.ndarray, rho: Optional[np.ndarray] = None) -> np.ndarray:
     """dJ/drho = chi p rho^(p-1) M0 . A  (explicit dJ/drho is zero for these objectives)."""
     rho = w.rho if rho is None else rho
-    chi = box_mask(w.n, w.design)
+    chi = design_chi(w)
     return chi * w.p * ipow(rho, w.p - 1) * np.sum(m0_array(w) * A, axis=0)
 
 
@@ -329,3 +345,20 @@ def objective_and_grad(w, rho: Optional[np.ndarray] = None, table: Optional[np.n
     J, g = objective(w, H)
     A = adjoint_field(w, g, table=table)
     return J, gradient_from_adjoint(w, A, rho), H
+
+
+def project_step(w, rho: np.ndarray, grad: np.ndarray, alpha: float) -> np.ndarray:
+    """One projected-gradient update of the density (a new array):
+
+        rho_j <- min(1, max(0, rho_j - alpha * grad_j / G)),  G = max over chi of |grad|,
+
+    on the design cells j (chi_j = 1); every other cell keeps its value, and
+    G = 0 leaves rho unchanged.  FP64."""
+    chi = design_chi(w) != 0
+    rho = np.asarray(rho, dtype=np.float64)
+    grad = np.asarray(grad, dtype=np.float64)
+    G = float(np.abs(grad[chi]).max()) if chi.any() else 0.0
+    if G == 0.0:
+        return rho.copy()
+    moved = np.minimum(1.0, np.maximum(0.0, rho - alpha * grad / G))
+    return np.where(chi, moved, rho)

@@ -54,6 +54,7 @@ class Workload:
     j_lambda: float = 0.01
     h_target: Optional[np.ndarray] = None               # [3][sensor cells] (C4)
     pad: Optional[Tuple[int, int, int]] = None          # padded FFT lengths (None: rule)
+    mask: Optional[np.ndarray] = None                   # [nz][ny][nx] uint8: design cells are box and mask != 0
 
     @property
     def cells(self) -> int:
@@ -192,6 +193,13 @@ def small_random(seed: int, n=(12, 10, 14), h=(1.0, 1.0, 1.0), design=None, sens
                     rho=rho, m0=m0, m0_field=m0_field, j_kind=j_kind, j_target=0.2,
                     j_lambda={J_MEAN_SQ_HZ_GRADXY: 0.01, J_FIELD_GRADIENT: 0.5}.get(j_kind, 0.0),
                     h_target=ht)
+
+
+def random_mask(seed: int, n, fraction: float = 0.7) -> np.ndarray:
+    """A seeded uint8 design mask [nz][ny][nx]: each cell kept with probability `fraction`."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    return (rng.random((nz, ny, nx)) < fraction).astype(np.uint8)
 
 
 def by_name(name: str):
