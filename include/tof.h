@@ -74,15 +74,27 @@ typedef enum {
                                     neighbours must be in the grid */
 } tof_objective_kind;
 
-/* Grid: the FFT box of nx*ny*nz cells of size dx*dy*dz.  Lx, Ly, Lz are the
- * padded FFT lengths; 0 selects 2n, or, when 2n has a prime factor above 7,
- * the smallest even 7-smooth length above 2n.  Explicit lengths must be even,
- * 7-smooth, >= 2n - 1 and <= 1024 (so n <= 512 per axis). */
+/* Grid flags (tof_grid.flags). */
+#define TOF_GRID_SELFTEST_PERTURB 1  /* test hook: setup adds 1e-9 to the self term of N_xx before
+                                        its trace self-check, which must then fail (TOF_ERR_NUMERIC) */
+
+/* Grid: the FFT box of nx*ny*nz cells of size dx*dy*dz (the regular cuboid
+ * grid of Sec. Discretization).  Lx, Ly, Lz are the padded FFT lengths; 0
+ * selects 2n, or, when 2n has a prime factor above 7, the smallest even
+ * 7-smooth length above 2n.  Explicit lengths must be even, 7-smooth,
+ * >= 2n - 1 and <= 1024 (so n <= 512 per axis).
+ * validate = 1: every hot call first checks its input arrays for NaN and
+ * infinite values on the device, waits for that check and returns
+ * TOF_ERR_INVALID (launching nothing else) when it finds one; such calls
+ * synchronize their stream, so they cannot be captured into a graph.
+ * validate = 0 (the fast path): no check, non-finite inputs propagate. */
 typedef struct {
     int32_t nx, ny, nz;
     double dx, dy, dz;
     int32_t Lx, Ly, Lz;
     int32_t dtype;          /* tof_dtype */
+    int32_t validate;       /* 0 or 1 */
+    int32_t flags;          /* TOF_GRID_* bits, normally 0 */
 } tof_grid;
 
 /* Half-open cell index box [x0,x1) x [y0,y1) x [z0,z1). */
@@ -95,19 +107,26 @@ typedef struct {
     tof_box sensor;             /* sensor cells */
     double target;              /* t (kinds 1, 2) */
     double lambda_grad;         /* lam (kinds 2, 5) */
-    const double *h_target_host;/* kind 3: H* as [3][sensor cells], C order over the sensor box; else NULL */
+    const double *h_target_host;/* kind 3: H* as [3][sensor cells], C order over the sensor box, host memory */
+    const double *h_target_dev; /* kind 3: the same in device memory; give exactly one of the two (else both NULL) */
 } tof_objective;
 
 /*
  * tof_create -- validate the grid, pick FFT plans, allocate the workspaces
  * and compute the tensor spectra (setup; allowed to allocate and to block).
- * The demagnetization tensor (eq. (demag_tensor)) is evaluated on the GPU
- * from Newell's closed form in double-double arithmetic, wrapped onto the
- * padded box and transformed in FP64; the spectra are stored in the grid's
- * dtype.  On success *out owns all device memory of the context.
- * Errors: TOF_ERR_INVALID (null/empty/oversized grid, non-positive cell),
- * TOF_ERR_UNSUPPORTED (explicit L not 7-smooth or too small), TOF_ERR_OOM,
- * TOF_ERR_HIP, TOF_ERR_NUMERIC (tensor spectra not real to 1e-9 relative).
+ * The demagnetization tensor of Sec. Discretization, eq. (demag_tensor) (a
+ * function of the index difference only), is evaluated on the GPU from
+ * Newell's closed form in double-double arithmetic, wrapped onto the padded
+ * box and transformed in FP64 (the FFT acceleration of the text after that
+ * equation); the spectra are stored in the grid's dtype.  Self-checks before
+ * the context is returned: the real-space trace, max |tr N(k) - delta_k0| <
+ * 1e-12 over all offsets, and spectra that are real to 1e-9 relative.
+ * On success *out owns all device memory of the context (tof_ctx_bytes);
+ * setup also holds temporaries (about 30 bytes per padded cell) until it
+ * returns.  Blocks until setup is done.
+ * Errors: TOF_ERR_INVALID (null/empty/oversized grid, non-positive cell,
+ * bad validate/flags), TOF_ERR_UNSUPPORTED (explicit L not 7-smooth or too
+ * small), TOF_ERR_OOM, TOF_ERR_HIP, TOF_ERR_NUMERIC (a self-check failed).
  */
 tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out);
 
@@ -115,7 +134,10 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out);
 void tof_destroy(tof_ctx *ctx);
 
 /*
- * tof_set_design -- the design region chi and magnetization M = chi rho^p M0.
+ * tof_set_design -- the design region chi and magnetization M = chi rho^p M0
+ * (Sec. Methodology: the penalized magnetization M(rho) = rho^p M0 with M0
+ * constant or spatially varying; chi the characteristic function of the
+ * design region).
  *  design:   index box of design cells (NULL = whole grid).
  *  mask:     optional device uint8 [nz][ny][nx]; chi = box && mask != 0.
  *  m0_host:  uniform M0 (3 doubles); ignored when m0_field is given.
@@ -128,14 +150,21 @@ tof_status tof_set_design(tof_ctx *ctx, const tof_box *design, const uint8_t *ma
                           const double m0_host[3], const void *m0_field, int32_t p);
 
 /*
- * tof_set_objective -- the objective J and its sensor cells.  Copies
- * h_target_host to the device.  Errors: TOF_ERR_INVALID (box outside the
- * grid, missing x/y neighbours for kind 2, missing H* for kind 3).
+ * tof_set_objective -- the objective J(H) of Sec. Methodology,
+ * eq. (objective_function), one of the kinds above, and its sensor cells.
+ * Copies H* (kind 3) into the context (synchronously).  The context keeps no
+ * pointer of `obj`.  Errors: TOF_ERR_INVALID (box outside the grid, missing
+ * x/y neighbours for kinds 2 and 5, not exactly one H* for kind 3; the
+ * previous objective stays), TOF_ERR_OOM / TOF_ERR_HIP (the context is then
+ * left without an objective: hot calls that need one return TOF_ERR_STATE).
  */
 tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj);
 
 /*
- * tof_field -- H = -N (*) (chi rho^p M0) on the whole grid.
+ * tof_field -- H = -N (*) (chi rho^p M0) on the whole grid: the discrete
+ * convolution of Sec. Discretization, eq. (convolution), with the tensor of
+ * eq. (demag_tensor), computed as a zero-padded FFT convolution (the text
+ * after eq. (demag_tensor)); the stray-field operator D of Sec. Methodology.
  *  rho:        device [nz][ny][nx].
  *  H:          device [c][nz][ny][nx], c = number of bits in comps_mask
  *              (bit 0 = Hx, bit 1 = Hy, bit 2 = Hz), in component order.
@@ -144,9 +173,13 @@ tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj);
 tof_status tof_field(tof_ctx *ctx, const void *rho, void *H, int32_t comps_mask, void *stream);
 
 /*
- * tof_objective_and_grad -- one gradient evaluation: forward field on the
- * cells J reads, J (FP64, fixed-order reduction), g = dJ/dH, the adjoint
- * field A = -N (*) g on the design cells, dJ/drho = chi p rho^(p-1) M0 . A.
+ * tof_objective_and_grad -- one gradient evaluation of Sec. Methodology:
+ * J^(rho) = J(H(rho), rho) (eq. (objective_function)) and its derivative
+ * through the adjoint problem (eqs. (dj_drho), (adjoint1), (adjoint2)),
+ * solved with the same stray-field operator as the forward problem:
+ * forward field on the cells J reads, J (FP64, fixed-order reduction),
+ * g = dJ/dH, the adjoint field A = -N (*) g on the design cells,
+ * dJ/drho = chi p rho^(p-1) M0 . A.
  *  rho:  device [nz][ny][nx].
  *  J:    device double[1] (may be NULL).
  *  grad: device [nz][ny][nx]; zero outside the design region.
@@ -156,7 +189,8 @@ tof_status tof_objective_and_grad(tof_ctx *ctx, const void *rho, double *J, void
                                   void *stream);
 
 /*
- * tof_adjoint -- vector-Jacobian product of tof_field: given any gH =
+ * tof_adjoint -- vector-Jacobian product of tof_field (the adjoint solve of
+ * Sec. Methodology with a given dL/dH in place of dJ/dH): given any gH =
  * dL/dH as device [3][nz][ny][nx], writes dL/drho = chi p rho^(p-1) M0 .
  * (-N (*) gH) to grad [nz][ny][nx] (zero outside the design region).
  * Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_HIP.
@@ -164,10 +198,14 @@ tof_status tof_objective_and_grad(tof_ctx *ctx, const void *rho, double *J, void
 tof_status tof_adjoint(tof_ctx *ctx, const void *rho, const void *gH, void *grad, void *stream);
 
 /*
- * tof_project_step -- one projected-gradient update on the design cells,
- * rho <- clamp(rho - alpha grad / max|grad|, 0, 1); cells outside the design
- * region are left unchanged; a zero gradient leaves rho unchanged.
- * rho, grad: device [nz][ny][nx].  Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_HIP.
+ * tof_project_step -- one projected-gradient update that keeps rho in the
+ * bounds 0 <= rho <= 1 of Sec. Methodology (the paper minimizes with a
+ * bound-constrained quasi-Newton method, Sec. Discretization; this is the
+ * simplest such step): on the design cells chi (box and mask),
+ * rho <- clamp(rho - alpha grad / G, 0, 1), G = max over chi of |grad|;
+ * other cells are left unchanged; G = 0 leaves rho unchanged.
+ * rho (updated in place), grad: device [nz][ny][nx]; alpha >= 0.
+ * Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_HIP.
  */
 tof_status tof_project_step(tof_ctx *ctx, void *rho, const void *grad, double alpha, void *stream);
 
@@ -244,8 +282,18 @@ tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value);
 /* Padded lengths chosen for the context: out[0..2] = Lx, Ly, Lz. */
 tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3]);
 
-/* Device bytes the context holds (workspaces and spectra). */
-size_t tof_workspace_bytes(const tof_ctx *ctx);
+/*
+ * Device bytes a context for `grid` holds once tof_create has returned
+ * (spectra, workspaces, twiddle tables, small buffers), computed on the host
+ * without creating anything: a caller can size memory first.  Setup needs
+ * its temporaries on top (see tof_create), and tof_set_objective adds the
+ * objective's buffers (a few words per sensor cell).  0 for an invalid grid
+ * (tof_last_error(NULL) says why).
+ */
+size_t tof_workspace_bytes(const tof_grid *grid);
+
+/* Device bytes a context holds now (workspaces, spectra, objective buffers). */
+size_t tof_ctx_bytes(const tof_ctx *ctx);
 
 /* Last error message of the context (or of this thread when ctx is NULL). */
 const char *tof_last_error(const tof_ctx *ctx);

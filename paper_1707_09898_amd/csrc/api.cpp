@@ -63,8 +63,11 @@ struct tof_ctx {
     BlockMap bmap{};   // layout of B: [c][kx][ky / KB][z][ky % KB]
     // objective buffers
     DeviceBuf Hs, G, Ht;
-    DeviceBuf scratch64;
+    DeviceBuf scratch64;          // [0] validation flag
+    DeviceBuf steppart;           // projected step: per-block partial maxima (kStepMaxBlocks doubles)
     DeviceBuf partials, ticket;   // objective: per-block partial sums, completion counter (kept at 0)
+    bool validate = false;        // hot calls reject non-finite inputs (and synchronize)
+    int flags = 0;                // tof_grid.flags
     // design
     bool has_design = false;
     Box design{};
@@ -94,6 +97,9 @@ struct tof_ctx {
 namespace {
 
 constexpr int kProfCalls = 1024;
+// largest |tr N(k) - delta_k0| the setup accepts (the FP64 tensor entries are
+// each within half an ulp of |N| <= 1 after the double-double evaluation)
+constexpr double kTraceTol = 1e-12;
 // Row groups of the fused y / z-sum kernels (blocks = groups x (Lx/2+1)).
 // At 256x256x128 the gather (whose groups the objective kernel adds) runs
 // best with 6 among 4 to 8, the scatter with 8 among 4, 8 and 16.
@@ -173,6 +179,71 @@ std::vector<int> factor_radices(int L)
     for (int f : {3, 5, 7})
         while (L % f == 0) { r.push_back(f); L /= f; }
     return r;
+}
+
+// Everything tof_create derives from a grid: padded lengths, the layout of
+// the spectra and the bytes of every buffer it allocates.
+struct GridLayout {
+    int L[3] = {0, 0, 0};
+    int hx = 0, hkz = 0, ky_pitch = 0, kt_pitch = 0;
+    long long comp_stride = 0, comp_stride_kt = 0;
+    size_t wsize = 4;
+    size_t spec = 0, kt = 0, A = 0, B = 0, C = 0, small = 0;
+    size_t total() const { return spec + kt + A + B + C + small; }
+};
+
+tof_status grid_layout(const tof_grid &g, GridLayout &out, std::string &err)
+{
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > kMaxL / 2 || g.ny > kMaxL / 2 || g.nz > kMaxL / 2) {
+        err = "grid sizes must be in [1, 512]";
+        return TOF_ERR_INVALID;
+    }
+    if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !std::isfinite(g.dx) || !std::isfinite(g.dy) ||
+        !std::isfinite(g.dz)) {
+        err = "cell sizes must be positive and finite";
+        return TOF_ERR_INVALID;
+    }
+    if (g.dtype != TOF_F32 && g.dtype != TOF_F64) {
+        err = "dtype must be TOF_F32 or TOF_F64";
+        return TOF_ERR_INVALID;
+    }
+    if (g.validate != 0 && g.validate != 1) {
+        err = "validate must be 0 or 1";
+        return TOF_ERR_INVALID;
+    }
+    if (g.flags & ~TOF_GRID_SELFTEST_PERTURB) {
+        err = "unknown grid flags";
+        return TOF_ERR_INVALID;
+    }
+    int L[3] = {g.Lx, g.Ly, g.Lz};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (L[a] == 0) L[a] = choose_length(n[a]);
+        if (L[a] < 2 * n[a] - 1 || L[a] > kMaxL || !smooth7(L[a]) || (L[a] & 1)) {
+            err = "padded length must be even, 7-smooth, >= 2n-1 and <= 1024 (axis " + std::to_string(a) + ")";
+            return TOF_ERR_UNSUPPORTED;
+        }
+        out.L[a] = L[a];
+    }
+    out.wsize = g.dtype == TOF_F64 ? 8 : 4;
+    out.hx = L[0] / 2 + 1;
+    out.hkz = L[2] / 2 + 1;
+    out.ky_pitch = ((L[1] / 2 + 1) + 15) / 16 * 16;
+    out.comp_stride = (long long)out.hx * out.hkz * out.ky_pitch;
+    out.kt_pitch = (L[1] + 31) / 32 * 32;
+    out.comp_stride_kt = (long long)out.hx * g.nz * out.kt_pitch;
+    const size_t cw = 2 * out.wsize;
+    out.spec = out.wsize * 6 * (size_t)out.comp_stride;
+    out.kt = out.wsize * 6 * (size_t)out.comp_stride_kt;
+    out.A = cw * 3 * (size_t)out.hx * g.nz * g.ny;
+    out.B = cw * 3 * (size_t)out.hx * g.nz * L[1];
+    out.C = cw * 3 * (size_t)out.hx * g.nz * g.ny;
+    // twiddle tables (FP32 and FP64 per axis), scratch words, step partials,
+    // objective block sums and counter
+    size_t tw = 0;
+    for (int a = 0; a < 3; ++a) tw += (sizeof(float) + sizeof(double)) * 2 * (size_t)L[a];
+    out.small = tw + 64 + sizeof(double) * kStepMaxBlocks + sizeof(double) * kObjMaxBlocks + 64;
+    return TOF_OK;
 }
 
 tof_status dev_alloc(tof_ctx *ctx, DeviceBuf &b, size_t bytes)
@@ -542,16 +613,19 @@ tof_status compute_spectra(tof_ctx *ctx, hipStream_t st)
     const int nx = ctx->nx, ny = ctx->ny, nz = ctx->nz;
     const int Lx = ctx->Lx, Ly = ctx->Ly, Lz = ctx->Lz, hx = ctx->hx;
     const int lx = nx + 1, ly = ny + 1, lz = nz + 1;
-    DeviceBuf lat, W, A64, B64, bits;
+    DeviceBuf lat, W, A64, B64, bits, T;
     struct Guard {
-        DeviceBuf *b[5];
+        DeviceBuf *b[6];
         ~Guard()
         {
             for (DeviceBuf *x : b)
                 if (x->p) (void)hipFree(x->p);
         }
-    } guard{{&lat, &W, &A64, &B64, &bits}};
+    } guard{{&lat, &W, &A64, &B64, &bits, &T}};
     tof_status s;
+    const long long noct = (long long)nx * ny * nz;
+    if ((s = dev_alloc(ctx, T, sizeof(double) * (size_t)noct)) != TOF_OK) return s;
+    HIP_TRY(ctx, hipMemsetAsync(T.p, 0, T.bytes, st));
     if ((s = dev_alloc(ctx, lat, sizeof(double) * 2 * (size_t)lx * ly * lz)) != TOF_OK) return s;
     if ((s = dev_alloc(ctx, W, sizeof(double) * (size_t)Lx * Ly * Lz)) != TOF_OK) return s;
     if ((s = dev_alloc(ctx, A64, sizeof(cplx<double>) * (size_t)hx * Lz * Ly)) != TOF_OK) return s;
@@ -572,6 +646,23 @@ tof_status compute_spectra(tof_ctx *ctx, hipStream_t st)
         HIP_TRY(ctx, hipMemsetAsync(W.p, 0, W.bytes, st));
         HIP_TRY(ctx, launch_newell_stencil(st, c, nx, ny, nz, lx, ly, ctx->dx, ctx->dy, ctx->dz,
                                            (const double *)lat.p, (double *)W.p, Lx, Ly, Lz, nullptr));
+        if (c == 0 && (ctx->flags & TOF_GRID_SELFTEST_PERTURB))
+            HIP_TRY(ctx, launch_add_at(st, (double *)W.p, 0, 1e-9));   // the self term of xx
+        if (c < 3) {
+            // the trace of the real-space tensor: tr N(k) = delta_k0
+            HIP_TRY(ctx, launch_trace_accumulate(st, (const double *)W.p, Lx, Ly, nx, ny, nz, (double *)T.p));
+            if (c == 2) {
+                HIP_TRY(ctx, launch_trace_error(st, (const double *)T.p, noct, (unsigned long long *)bits.p));
+                unsigned long long hb;
+                HIP_TRY(ctx, hipMemcpyAsync(&hb, bits.p, sizeof(hb), hipMemcpyDeviceToHost, st));
+                HIP_TRY(ctx, hipStreamSynchronize(st));
+                double terr;
+                std::memcpy(&terr, &hb, 8);
+                if (!(terr < kTraceTol))
+                    return fail(ctx, TOF_ERR_NUMERIC, "tensor trace self-check failed: max |tr N(k) - delta_k0| = " +
+                                                          std::to_string(terr));
+            }
+        }
         HIP_TRY(ctx, launch_x_forward<double>(st, SRC_ARRAY, nodsg, wsrc, whole, 1, plx, (cplx<double> *)A64.p, hx));
         const BlockMap plain{30, 0, Ly};
         HIP_TRY(ctx, launch_line_fft<double>(st, (const cplx<double> *)A64.p, (cplx<double> *)B64.p, hx * Lz, Lz,
@@ -626,7 +717,7 @@ void release(tof_ctx *ctx)
     for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
     ctx->prof_ev.clear();
     DeviceBuf *bufs[] = {&ctx->spec, &ctx->kt, &ctx->A, &ctx->B, &ctx->C, &ctx->Hs, &ctx->G, &ctx->Ht,
-                         &ctx->scratch64, &ctx->partials, &ctx->ticket};
+                         &ctx->scratch64, &ctx->steppart, &ctx->partials, &ctx->ticket};
     for (DeviceBuf *b : bufs)
         if (b->p) {
             (void)hipFree(b->p);
@@ -647,6 +738,26 @@ tof_status check_ready(tof_ctx *ctx, bool need_obj)
     return TOF_OK;
 }
 
+// With validation on: TOF_ERR_INVALID when any of the n values of `a` is NaN
+// or infinite (a device check, then a wait for its one-word result).
+template <typename R>
+tof_status check_finite(tof_ctx *ctx, hipStream_t st, const void *a, long long n, const char *what)
+{
+    if (!ctx->validate) return TOF_OK;
+    unsigned long long *flag = (unsigned long long *)ctx->scratch64.p;
+    HIP_TRY(ctx, launch_nonfinite<R>(st, (const R *)a, n, flag));
+    unsigned long long h = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (h) return fail(ctx, TOF_ERR_INVALID, std::string(what) + " holds NaN or infinite values");
+    return TOF_OK;
+}
+
+tof_status check_finite_any(tof_ctx *ctx, hipStream_t st, const void *a, long long n, const char *what)
+{
+    return ctx->f64 ? check_finite<double>(ctx, st, a, n, what) : check_finite<float>(ctx, st, a, n, what);
+}
+
 }  // namespace
 
 extern "C" {
@@ -657,31 +768,23 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
     *out = nullptr;
     if (!grid) return fail(nullptr, TOF_ERR_INVALID, "grid is null");
     const tof_grid g = *grid;
-    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > kMaxL / 2 || g.ny > kMaxL / 2 || g.nz > kMaxL / 2)
-        return fail(nullptr, TOF_ERR_INVALID, "grid sizes must be in [1, 512]");
-    if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !std::isfinite(g.dx) || !std::isfinite(g.dy) ||
-        !std::isfinite(g.dz))
-        return fail(nullptr, TOF_ERR_INVALID, "cell sizes must be positive and finite");
-    if (g.dtype != TOF_F32 && g.dtype != TOF_F64) return fail(nullptr, TOF_ERR_INVALID, "dtype must be TOF_F32 or TOF_F64");
-    int L[3] = {g.Lx, g.Ly, g.Lz};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    for (int a = 0; a < 3; ++a) {
-        if (L[a] == 0) L[a] = choose_length(n[a]);
-        if (L[a] < 2 * n[a] - 1 || L[a] > kMaxL || !smooth7(L[a]) || (L[a] & 1))
-            return fail(nullptr, TOF_ERR_UNSUPPORTED,
-                        "padded length must be even, 7-smooth, >= 2n-1 and <= 1024 (axis " + std::to_string(a) + ")");
-    }
+    GridLayout lay;
+    std::string lerr;
+    tof_status s = grid_layout(g, lay, lerr);
+    if (s != TOF_OK) return fail(nullptr, s, lerr);
+    const int *L = lay.L;
     tof_ctx *ctx = new (std::nothrow) tof_ctx();
     if (!ctx) return fail(nullptr, TOF_ERR_OOM, "host allocation failed");
     ctx->nx = g.nx; ctx->ny = g.ny; ctx->nz = g.nz;
     ctx->dx = g.dx; ctx->dy = g.dy; ctx->dz = g.dz;
     ctx->Lx = L[0]; ctx->Ly = L[1]; ctx->Lz = L[2];
-    ctx->hx = L[0] / 2 + 1;
+    ctx->hx = lay.hx;
     ctx->f64 = g.dtype == TOF_F64;
-    ctx->wsize = ctx->f64 ? 8 : 4;
+    ctx->wsize = lay.wsize;
+    ctx->validate = g.validate != 0;
+    ctx->flags = g.flags;
     ctx->design = Box{0, g.nx, 0, g.ny, 0, g.nz};
     hipStream_t st = (hipStream_t)stream;
-    tof_status s;
     auto bail = [&](tof_status code) {
         release(ctx);
         g_thread_error = ctx->err;
@@ -691,13 +794,13 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
     if ((s = make_plan(ctx, ctx->px, L[0])) != TOF_OK) return bail(s);
     if ((s = make_plan(ctx, ctx->py, L[1])) != TOF_OK) return bail(s);
     if ((s = make_plan(ctx, ctx->pz, L[2])) != TOF_OK) return bail(s);
-    ctx->hkz = L[2] / 2 + 1;
-    ctx->ky_pitch = ((L[1] / 2 + 1) + 15) / 16 * 16;
-    ctx->comp_stride = (long long)ctx->hx * ctx->hkz * ctx->ky_pitch;
-    ctx->kt_pitch = (L[1] + 31) / 32 * 32;
-    ctx->comp_stride_kt = (long long)ctx->hx * g.nz * ctx->kt_pitch;
-    if ((s = dev_alloc(ctx, ctx->spec, ctx->wsize * 6 * (size_t)ctx->comp_stride)) != TOF_OK) return bail(s);
-    if ((s = dev_alloc(ctx, ctx->kt, ctx->wsize * 6 * (size_t)ctx->comp_stride_kt)) != TOF_OK) return bail(s);
+    ctx->hkz = lay.hkz;
+    ctx->ky_pitch = lay.ky_pitch;
+    ctx->comp_stride = lay.comp_stride;
+    ctx->kt_pitch = lay.kt_pitch;
+    ctx->comp_stride_kt = lay.comp_stride_kt;
+    if ((s = dev_alloc(ctx, ctx->spec, lay.spec)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->kt, lay.kt)) != TOF_OK) return bail(s);
     ctx->Zrows = g.nz;
     {
         // ky-blocked B (KB columns of 256 bytes) when both the y and the z
@@ -711,11 +814,11 @@ tof_status tof_create(const tof_grid *grid, void *stream, tof_ctx **out)
         else
             ctx->bmap = BlockMap{30, 0, L[1]};
     }
-    const size_t cw = 2 * ctx->wsize;   // complex bytes
-    if ((s = dev_alloc(ctx, ctx->A, cw * 3 * (size_t)ctx->hx * g.nz * g.ny)) != TOF_OK) return bail(s);
-    if ((s = dev_alloc(ctx, ctx->B, cw * 3 * (size_t)ctx->hx * g.nz * L[1])) != TOF_OK) return bail(s);
-    if ((s = dev_alloc(ctx, ctx->C, cw * 3 * (size_t)ctx->hx * g.nz * g.ny)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->A, lay.A)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->B, lay.B)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->C, lay.C)) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->scratch64, 64)) != TOF_OK) return bail(s);
+    if ((s = dev_alloc(ctx, ctx->steppart, sizeof(double) * kStepMaxBlocks)) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->partials, sizeof(double) * kObjMaxBlocks)) != TOF_OK) return bail(s);
     if ((s = dev_alloc(ctx, ctx->ticket, 64)) != TOF_OK) return bail(s);
     {
@@ -778,10 +881,12 @@ tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj)
             return fail(ctx, TOF_ERR_INVALID, "the gradient strip and its outer neighbours must be in the grid");
         ob = Box{sb.x0 - 2, sb.x1 + 2, sb.y0 - 2, sb.y1, sb.z0, sb.z1};
     }
-    if (obj->kind == TOF_J_MEAN_SQ_H_TARGET && !obj->h_target_host)
-        return fail(ctx, TOF_ERR_INVALID, "kind 3 needs h_target_host");
+    if (obj->kind == TOF_J_MEAN_SQ_H_TARGET && !obj->h_target_host == !obj->h_target_dev)
+        return fail(ctx, TOF_ERR_INVALID, "kind 3 needs exactly one of h_target_host and h_target_dev");
     if (!std::isfinite(obj->target) || !std::isfinite(obj->lambda_grad))
         return fail(ctx, TOF_ERR_INVALID, "target and lambda must be finite");
+    // from here on a failure leaves the context without an objective
+    ctx->has_obj = false;
     const int cj = obj->kind == TOF_J_MEAN_SQ_H_TARGET ? 3 : 1;
     const size_t nob = (size_t)ob.nx() * ob.ny() * ob.nz();
     const size_t S = (size_t)sb.nx() * sb.ny() * sb.nz();
@@ -790,7 +895,10 @@ tof_status tof_set_objective(tof_ctx *ctx, const tof_objective *obj)
     if ((s = dev_alloc(ctx, ctx->G, ctx->wsize * cj * nob)) != TOF_OK) return s;
     if (obj->kind == TOF_J_MEAN_SQ_H_TARGET) {
         if ((s = dev_alloc(ctx, ctx->Ht, sizeof(double) * 3 * S)) != TOF_OK) return s;
-        HIP_TRY(ctx, hipMemcpy(ctx->Ht.p, obj->h_target_host, sizeof(double) * 3 * S, hipMemcpyHostToDevice));
+        if (obj->h_target_host)
+            HIP_TRY(ctx, hipMemcpy(ctx->Ht.p, obj->h_target_host, sizeof(double) * 3 * S, hipMemcpyHostToDevice));
+        else
+            HIP_TRY(ctx, hipMemcpy(ctx->Ht.p, obj->h_target_dev, sizeof(double) * 3 * S, hipMemcpyDeviceToDevice));
     }
     ctx->kind = obj->kind;
     ctx->sensor = sb;
@@ -808,6 +916,8 @@ tof_status tof_field(tof_ctx *ctx, const void *rho, void *H, int32_t comps_mask,
     if (!rho || !H) return fail(ctx, TOF_ERR_INVALID, "rho and H must be non-null");
     if (comps_mask < 1 || comps_mask > 7) return fail(ctx, TOF_ERR_INVALID, "comps_mask must be in [1, 7]");
     hipStream_t st = (hipStream_t)stream;
+    const long long n = (long long)ctx->nx * ctx->ny * ctx->nz;
+    if ((s = check_finite_any(ctx, st, rho, n, "rho")) != TOF_OK) return s;
     return ctx->f64 ? run_field<double>(ctx, st, rho, H, comps_mask) : run_field<float>(ctx, st, rho, H, comps_mask);
 }
 
@@ -817,6 +927,8 @@ tof_status tof_objective_and_grad(tof_ctx *ctx, const void *rho, double *J, void
     if (s != TOF_OK) return s;
     if (!rho || !grad) return fail(ctx, TOF_ERR_INVALID, "rho and grad must be non-null");
     hipStream_t st = (hipStream_t)stream;
+    const long long n = (long long)ctx->nx * ctx->ny * ctx->nz;
+    if ((s = check_finite_any(ctx, st, rho, n, "rho")) != TOF_OK) return s;
     return ctx->f64 ? run_objective_and_grad<double>(ctx, st, rho, J, grad)
                     : run_objective_and_grad<float>(ctx, st, rho, J, grad);
 }
@@ -828,6 +940,8 @@ tof_status tof_adjoint(tof_ctx *ctx, const void *rho, const void *gH, void *grad
     if (!rho || !gH || !grad) return fail(ctx, TOF_ERR_INVALID, "rho, gH and grad must be non-null");
     hipStream_t st = (hipStream_t)stream;
     const long long n = (long long)ctx->nx * ctx->ny * ctx->nz;
+    if ((s = check_finite_any(ctx, st, rho, n, "rho")) != TOF_OK) return s;
+    if ((s = check_finite_any(ctx, st, gH, 3 * n, "gH")) != TOF_OK) return s;
     const Box all{0, ctx->nx, 0, ctx->ny, 0, ctx->nz};
     if (ctx->f64) {
         View4<const double> src{(const double *)gH, n, (long long)ctx->ny * ctx->nx, ctx->nx, 0, 0, 0};
@@ -844,13 +958,16 @@ tof_status tof_project_step(tof_ctx *ctx, void *rho, const void *grad, double al
     if (!rho || !grad) return fail(ctx, TOF_ERR_INVALID, "rho and grad must be non-null");
     if (!std::isfinite(alpha) || alpha < 0) return fail(ctx, TOF_ERR_INVALID, "alpha must be finite and >= 0");
     hipStream_t st = (hipStream_t)stream;
-    unsigned long long *mb = (unsigned long long *)ctx->scratch64.p;
+    const long long n = (long long)ctx->nx * ctx->ny * ctx->nz;
+    if ((s = check_finite_any(ctx, st, rho, n, "rho")) != TOF_OK) return s;
+    if ((s = check_finite_any(ctx, st, grad, n, "grad")) != TOF_OK) return s;
+    double *part = (double *)ctx->steppart.p;
     if (ctx->f64)
-        HIP_TRY(ctx, launch_project_step<double>(st, (double *)rho, (const double *)grad, ctx->nx, ctx->ny, ctx->nz,
-                                                 ctx->design, alpha, mb));
+        HIP_TRY(ctx, launch_project_step<double>(st, (double *)rho, (const double *)grad, ctx->mask, ctx->nx, ctx->ny,
+                                                 ctx->nz, ctx->design, alpha, part));
     else
-        HIP_TRY(ctx, launch_project_step<float>(st, (float *)rho, (const float *)grad, ctx->nx, ctx->ny, ctx->nz,
-                                                ctx->design, alpha, mb));
+        HIP_TRY(ctx, launch_project_step<float>(st, (float *)rho, (const float *)grad, ctx->mask, ctx->nx, ctx->ny,
+                                                ctx->nz, ctx->design, alpha, part));
     return TOF_OK;
 }
 
@@ -937,11 +1054,25 @@ tof_status tof_padded_lengths(const tof_ctx *ctx, int32_t out[3])
     return TOF_OK;
 }
 
-size_t tof_workspace_bytes(const tof_ctx *ctx)
+size_t tof_workspace_bytes(const tof_grid *grid)
+{
+    if (!grid) return 0;
+    GridLayout lay;
+    std::string err;
+    if (grid_layout(*grid, lay, err) != TOF_OK) {
+        g_thread_error = err;
+        return 0;
+    }
+    return lay.total();
+}
+
+size_t tof_ctx_bytes(const tof_ctx *ctx)
 {
     if (!ctx) return 0;
+    size_t tw = 0;
+    for (const Plan1D *pl : {&ctx->px, &ctx->py, &ctx->pz}) tw += (sizeof(float) + sizeof(double)) * 2 * (size_t)pl->L;
     return ctx->spec.bytes + ctx->kt.bytes + ctx->A.bytes + ctx->B.bytes + ctx->C.bytes + ctx->Hs.bytes + ctx->G.bytes +
-           ctx->Ht.bytes + ctx->scratch64.bytes + ctx->partials.bytes + ctx->ticket.bytes;
+           ctx->Ht.bytes + ctx->scratch64.bytes + ctx->steppart.bytes + ctx->partials.bytes + ctx->ticket.bytes + tw;
 }
 
 const char *tof_last_error(const tof_ctx *ctx)

@@ -244,9 +244,26 @@ hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box s
                             double target, double lam, double dx, double dy, double vcell,
                             const double *h_target, double *J, R *g, double *partials, unsigned int *ticket);
 
+// Largest block count of the projected step (size of its partial-maxima buffer).
+constexpr int kStepMaxBlocks = 2048;
+
+// rho <- clamp(rho - alpha grad / G, 0, 1) on chi (design box and mask, if
+// not null), G = max over chi of |grad|; `part` holds kStepMaxBlocks doubles
+// of partial maxima (written by the first launch, read by the second).
 template <typename R>
-hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, int nx, int ny, int nz,
-                               Box design, double alpha, unsigned long long *maxbits);
+hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, const uint8_t *mask, int nx, int ny, int nz,
+                               Box design, double alpha, double *part);
+
+// *flag (one word) becomes 1 when any of the n values is NaN or infinite, else 0.
+template <typename R>
+hipError_t launch_nonfinite(hipStream_t st, const R *a, long long n, unsigned long long *flag);
+
+// Setup self-check of the tensor trace (FP64): T += the octant of a wrapped
+// component; then the largest |T - delta_0| as double bits.
+hipError_t launch_trace_accumulate(hipStream_t st, const double *wrapped, int Lx, int Ly, int nx, int ny, int nz,
+                                   double *T);
+hipError_t launch_trace_error(hipStream_t st, const double *T, long long n, unsigned long long *maxbits);
+hipError_t launch_add_at(hipStream_t st, double *a, long long idx, double v);
 
 hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, double dx,
                                  double dy, double dz, double *lat /* [lz][ly][lx][2] */);

@@ -837,10 +837,16 @@ __global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o,
 __global__ __launch_bounds__(64) void k_finalize_j(JFinal jf) { finalize_j(jf); }
 
 // ---------------------------------------------------------------------------
-// Projected gradient step on the design box.
+// Projected gradient step on the design cells chi (box and mask):
+// rho <- clamp(rho - alpha grad / G, 0, 1), G = max over chi of |grad|.
+// Two launches and no atomics: every block of the first writes the largest
+// |grad| of its cells to part[blockIdx.x] (all nb entries are written, so
+// nothing needs clearing between calls), and every block of the second
+// reduces the nb partial maxima itself (at most kStepMaxBlocks values) before
+// moving its cells.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_absmax(const R *grad, int nx, int ny, Box d,
-                                                   unsigned long long *maxbits)
+__global__ __launch_bounds__(kThreads) void k_absmax_part(const R *grad, const uint8_t *mask, int nx, int ny, Box d,
+                                                        double *part)
 {
     const long long n = (long long)d.nx() * d.ny() * d.nz();
     double m = 0.0;
@@ -849,23 +855,32 @@ __global__ __launch_bounds__(kThreads) void k_absmax(const R *grad, int nx, int 
         const int x = d.x0 + (int)(i % d.nx());
         const int y = d.y0 + (int)((i / d.nx()) % d.ny());
         const int z = d.z0 + (int)(i / ((long long)d.nx() * d.ny()));
-        m = fmax(m, fabs((double)grad[((long long)z * ny + y) * nx + x]));
+        const long long idx = ((long long)z * ny + y) * nx + x;
+        if (!mask || mask[idx]) m = fmax(m, fabs((double)grad[idx]));
     }
-    // non-negative doubles order like their bit patterns
-    atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
-}
-
-__global__ void k_clear_u64(unsigned long long *p, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    __shared__ double wmax[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wmax[0];
+        for (int w = 1; w < kThreads / 64; ++w) b = fmax(b, wmax[w]);
+        part[blockIdx.x] = b;
+    }
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_project(R *rho, const R *grad, int nx, int ny, Box d,
-                                                    double alpha, const unsigned long long *maxbits)
+__global__ __launch_bounds__(kThreads) void k_project(R *rho, const R *grad, const uint8_t *mask, int nx, int ny,
+                                                    Box d, double alpha, const double *part, int nb)
 {
-    const double gmax = __longlong_as_double((long long)*maxbits);
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, part[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    __shared__ double wmax[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    double gmax = wmax[0];
+    for (int w = 1; w < kThreads / 64; ++w) gmax = fmax(gmax, wmax[w]);
     if (!(gmax > 0.0)) return;
     const double step = alpha / gmax;
     const long long n = (long long)d.nx() * d.ny() * d.nz();
@@ -875,9 +890,27 @@ __global__ __launch_bounds__(kThreads) void k_project(R *rho, const R *grad, int
         const int y = d.y0 + (int)((i / d.nx()) % d.ny());
         const int z = d.z0 + (int)(i / ((long long)d.nx() * d.ny()));
         const long long idx = ((long long)z * ny + y) * nx + x;
+        if (mask && !mask[idx]) continue;
         const R v = rho[idx] - (R)(step * (double)grad[idx]);
         rho[idx] = v < (R)0 ? (R)0 : (v > (R)1 ? (R)1 : v);
     }
+}
+
+__global__ void k_clear_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Sets *flag to 1 when any of the n values is NaN or infinite.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_nonfinite(const R *a, long long n, unsigned long long *flag)
+{
+    bool bad = false;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        bad |= !isfinite((double)a[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,6 +981,40 @@ __global__ __launch_bounds__(128) void k_newell_stencil(int c, int mx, int my, i
             }
         }
     }
+}
+
+// Setup self-check of the trace: T[q] += N_c(k) for the octant offsets
+// 0 <= k < n (q in C order), read from the wrapped array; after the three
+// diagonal components T holds tr N(k), which is 1 at k = 0 (the self term of
+// any cuboid) and 0 elsewhere (the Laplacian of 1/r vanishes off the origin).
+__global__ __launch_bounds__(kThreads) void k_trace_accumulate(const double *wrapped, int Lx, int Ly, int nx, int ny,
+                                                             int nz, double *T)
+{
+    const long long n = (long long)nx * ny * nz;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % nx);
+        const int j = (int)((q / nx) % ny);
+        const int k = (int)(q / ((long long)nx * ny));
+        T[q] += wrapped[((long long)k * Ly + j) * Lx + i];
+    }
+}
+
+// Largest |T[q] - delta_q0| as bits of a non-negative double (atomic max).
+__global__ __launch_bounds__(kThreads) void k_trace_error(const double *T, long long n, unsigned long long *maxbits)
+{
+    double m = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(T[q] - (q == 0 ? 1.0 : 0.0)));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+}
+
+// One value added to one element (the test hook that perturbs the tensor).
+__global__ void k_add_at(double *a, long long idx, double v)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) a[idx] += v;
 }
 
 // Real part of the forward transform on the frequency octant, times `scale`,
@@ -2002,18 +2069,56 @@ hipError_t launch_objective(hipStream_t st, int kind, const R *Hs, Box ob, Box s
     return hipGetLastError();
 }
 
+static int step_blocks(Box design)
+{
+    const long long n = (long long)design.nx() * design.ny() * design.nz();
+    long long blocks = (n + kThreads - 1) / kThreads;
+    return (int)(blocks > kStepMaxBlocks ? kStepMaxBlocks : (blocks < 1 ? 1 : blocks));
+}
+
 template <typename R>
-hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, int nx, int ny, int nz,
-                               Box design, double alpha, unsigned long long *maxbits)
+hipError_t launch_project_step(hipStream_t st, R *rho, const R *grad, const uint8_t *mask, int nx, int ny, int nz,
+                               Box design, double alpha, double *part)
 {
     (void)nz;
-    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, maxbits, 1);
-    const long long n = (long long)design.nx() * design.ny() * design.nz();
-    int blocks = (int)((n + kThreads - 1) / kThreads);
+    const int blocks = step_blocks(design);
+    TOF_LAUNCH(k_absmax_part<R>, dim3(blocks), dim3(kThreads), 0, st, grad, mask, nx, ny, design, part);
+    TOF_LAUNCH(k_project<R>, dim3(blocks), dim3(kThreads), 0, st, rho, grad, mask, nx, ny, design, alpha, part,
+               blocks);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_nonfinite(hipStream_t st, const R *a, long long n, unsigned long long *flag)
+{
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, flag, 1);
+    long long blocks = (n + kThreads - 1) / kThreads;
     blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
-    TOF_LAUNCH(k_absmax<R>, dim3(blocks), dim3(kThreads), 0, st, grad, nx, ny, design, maxbits);
-    TOF_LAUNCH(k_project<R>, dim3(blocks), dim3(kThreads), 0, st, rho, grad, nx, ny, design, alpha,
-                       maxbits);
+    TOF_LAUNCH(k_nonfinite<R>, dim3((int)blocks), dim3(kThreads), 0, st, a, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_accumulate(hipStream_t st, const double *wrapped, int Lx, int Ly, int nx, int ny, int nz,
+                                   double *T)
+{
+    long long blocks = ((long long)nx * ny * nz + kThreads - 1) / kThreads;
+    blocks = blocks > 65536 ? 65536 : blocks;
+    TOF_LAUNCH(k_trace_accumulate, dim3((int)blocks), dim3(kThreads), 0, st, wrapped, Lx, Ly, nx, ny, nz, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_error(hipStream_t st, const double *T, long long n, unsigned long long *maxbits)
+{
+    TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, maxbits, 1);
+    long long blocks = (n + kThreads - 1) / kThreads;
+    blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
+    TOF_LAUNCH(k_trace_error, dim3((int)blocks), dim3(kThreads), 0, st, T, n, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_at(hipStream_t st, double *a, long long idx, double v)
+{
+    TOF_LAUNCH(k_add_at, dim3(1), dim3(64), 0, st, a, idx, v);
     return hipGetLastError();
 }
 
@@ -2129,8 +2234,9 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
     template hipError_t launch_objective<R>(hipStream_t, int, const R *, Box, Box, int, double, double,  \
                                             double, double, double, const double *, double *, R *,       \
                                             double *, unsigned int *);                                   \
-    template hipError_t launch_project_step<R>(hipStream_t, R *, const R *, int, int, int, Box, double,  \
-                                               unsigned long long *);                                          \
+    template hipError_t launch_project_step<R>(hipStream_t, R *, const R *, const uint8_t *, int, int, int, \
+                                               Box, double, double *);                                   \
+    template hipError_t launch_nonfinite<R>(hipStream_t, const R *, long long, unsigned long long *);      \
     template hipError_t launch_z_sum<R>(hipStream_t, cplx<R> *, int, int, int, int, int, int, int,       \
                                         const KtDev<R> &, const ProductDev &, BlockMap);                 \
     template hipError_t launch_extract_kt<R>(hipStream_t, const cplx<double> *, int, int, int, int, double, \

@@ -22,10 +22,11 @@ STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TO
 
 EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "tof_field",
            "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
-           "tof_padded_lengths", "tof_workspace_bytes", "tof_last_error", "tof_dd_newell_host",
+           "tof_padded_lengths", "tof_workspace_bytes", "tof_ctx_bytes", "tof_last_error", "tof_dd_newell_host",
            "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option"]
 
 OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE = 1, 2, 3
+GRID_SELFTEST_PERTURB = 1
 
 PROFILE_SLOTS = 12
 PROFILE_NAMES = ["fwd_x", "fwd_y", "fwd_z_product", "fwd_inv_y", "fwd_inv_x_field", "objective",
@@ -42,7 +43,7 @@ class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
-                ("dtype", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("validate", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class BoxC(ctypes.Structure):
@@ -51,7 +52,8 @@ class BoxC(ctypes.Structure):
 
 class Objective(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("sensor", BoxC), ("target", ctypes.c_double),
-                ("lambda_grad", ctypes.c_double), ("h_target_host", ctypes.POINTER(ctypes.c_double))]
+                ("lambda_grad", ctypes.c_double), ("h_target_host", ctypes.POINTER(ctypes.c_double)),
+                ("h_target_dev", ctypes.c_void_p)]
 
 
 _lib = None
@@ -77,8 +79,10 @@ def lib():
         L.tof_project_step.argtypes = [vp, vp, vp, dbl, vp]
         L.tof_tensor.argtypes = [vp, vp, vp]
         L.tof_padded_lengths.argtypes = [vp, ctypes.POINTER(i32)]
-        L.tof_workspace_bytes.argtypes = [vp]
+        L.tof_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.tof_workspace_bytes.restype = ctypes.c_size_t
+        L.tof_ctx_bytes.argtypes = [vp]
+        L.tof_ctx_bytes.restype = ctypes.c_size_t
         L.tof_last_error.argtypes = [vp]
         L.tof_last_error.restype = ctypes.c_char_p
         L.tof_dd_newell_host.argtypes = [i32, i32, i32, i32, dbl, dbl, dbl]
@@ -110,15 +114,13 @@ class Engine:
     """One context: a grid, its FFT plans, workspaces and tensor spectra."""
 
     def __init__(self, n: Sequence[int], h: Sequence[float], dtype: str = "f32",
-                 L: Optional[Sequence[int]] = None, stream=None):
+                 L: Optional[Sequence[int]] = None, stream=None, validate: bool = False, flags: int = 0):
         import torch
         self.torch = torch
         self.n = tuple(int(v) for v in n)
         self.h = tuple(float(v) for v in h)
         self.dtype = {"f32": torch.float32, "f64": torch.float64}[dtype]
-        Lx, Ly, Lz = (0, 0, 0) if L is None else (int(v) for v in L)
-        g = Grid(self.n[0], self.n[1], self.n[2], self.h[0], self.h[1], self.h[2], Lx, Ly, Lz,
-                 TOF_F32 if dtype == "f32" else TOF_F64)
+        g = make_grid(self.n, self.h, dtype, L, validate, flags)
         self._ctx = ctypes.c_void_p()
         self._keep = {}
         st = lib().tof_create(ctypes.byref(g), _stream_ptr(stream), ctypes.byref(self._ctx))
@@ -164,13 +166,19 @@ class Engine:
         self._check(lib().tof_set_design(self._ctx, bx, mk, m0a, mf, int(p)))
 
     def set_objective(self, kind: int, sensor, target: float = 0.0, lam: float = 0.0, h_target=None):
+        """h_target: H* for kind 3 as a host array, or a float64 cuda tensor
+        (passed as the device pointer), [3][sensor cells]."""
         import numpy as np
-        ptr = None
+        ptr, dptr = None, None
         if h_target is not None:
-            ht = np.ascontiguousarray(h_target, dtype=np.float64)
-            self._keep["h_target"] = ht
-            ptr = ht.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        obj = Objective(int(kind), _box(sensor), float(target), float(lam), ptr)
+            if isinstance(h_target, self.torch.Tensor) and h_target.device.type == "cuda":
+                x0, x1, y0, y1, z0, z1 = (int(v) for v in sensor)
+                dptr = self._arr(h_target, (3, z1 - z0, y1 - y0, x1 - x0), self.torch.float64)
+            else:
+                ht = np.ascontiguousarray(h_target, dtype=np.float64)
+                self._keep["h_target"] = ht
+                ptr = ht.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        obj = Objective(int(kind), _box(sensor), float(target), float(lam), ptr, dptr)
         self._check(lib().tof_set_objective(self._ctx, ctypes.byref(obj)))
 
     # -- hot calls --
@@ -240,20 +248,40 @@ class Engine:
         self._check(lib().tof_padded_lengths(self._ctx, out))
         return tuple(out)
 
-    def workspace_bytes(self) -> int:
-        return int(lib().tof_workspace_bytes(self._ctx))
+    def ctx_bytes(self) -> int:
+        """Device bytes the context holds (tof_ctx_bytes)."""
+        return int(lib().tof_ctx_bytes(self._ctx))
 
 
-def engine_for(w, dtype: str = "f32", stream=None, L=None) -> Engine:
+def make_grid(n, h, dtype: str = "f32", L=None, validate: bool = False, flags: int = 0) -> Grid:
+    Lx, Ly, Lz = (0, 0, 0) if L is None else (int(v) for v in L)
+    return Grid(int(n[0]), int(n[1]), int(n[2]), float(h[0]), float(h[1]), float(h[2]), Lx, Ly, Lz,
+                TOF_F32 if dtype == "f32" else TOF_F64, 1 if validate else 0, int(flags))
+
+
+def workspace_bytes(n, h, dtype: str = "f32", L=None) -> int:
+    """Device bytes a context for this grid holds after setup (tof_workspace_bytes;
+    host arithmetic only, no device needed).  Raises on an invalid grid."""
+    g = make_grid(n, h, dtype, L)
+    b = int(lib().tof_workspace_bytes(ctypes.byref(g)))
+    if b == 0:
+        raise TofError(-1, lib().tof_last_error(None).decode())
+    return b
+
+
+def engine_for(w, dtype: str = "f32", stream=None, L=None, validate: bool = False) -> Engine:
     """An Engine set up for a workload description (workloads.Workload); L
     overrides the workload's padded lengths."""
     import torch
-    e = Engine(w.n, w.h, dtype, L=w.pad if L is None else L, stream=stream)
+    e = Engine(w.n, w.h, dtype, L=w.pad if L is None else L, stream=stream, validate=validate)
     tdt = e.dtype
     m0f = None
     if w.m0_field is not None:
         m0f = torch.as_tensor(w.m0_field, dtype=tdt).contiguous().cuda()
-    e.set_design(w.design, m0=w.m0, m0_field=m0f, p=w.p)
+    mask = None
+    if getattr(w, "mask", None) is not None:
+        mask = torch.as_tensor(w.mask, dtype=torch.uint8).contiguous().cuda()
+    e.set_design(w.design, m0=w.m0, m0_field=m0f, p=w.p, mask=mask)
     e.set_objective(w.j_kind, w.sensor, w.j_target, w.j_lambda, w.h_target)
     return e
 

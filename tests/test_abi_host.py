@@ -39,6 +39,8 @@ def test_invalid_grids_are_rejected_before_any_launch():
            tof.Grid(4, 4, 4, 1, float("nan"), 1, 0, 0, 0, 1),
            tof.Grid(4, 4, 4, 1, 1, 1, 0, 0, 0, 3),
            tof.Grid(600, 4, 4, 1, 1, 1, 0, 0, 0, 1)]
+    bad += [tof.Grid(4, 4, 4, 1, 1, 1, 0, 0, 0, 1, 2, 0),      # validate must be 0 or 1
+            tof.Grid(4, 4, 4, 1, 1, 1, 0, 0, 0, 1, 0, 6)]      # unknown flag bits
     for g in bad:
         assert L.tof_create(ctypes.byref(g), None, ctypes.byref(ctx)) == -1
         assert ctx.value is None
@@ -62,6 +64,7 @@ def test_null_context_calls_fail_cleanly():
     assert L.tof_project_step(None, None, None, 0.1, None) == -1
     assert L.tof_tensor(None, None, None) == -1
     assert L.tof_workspace_bytes(None) == 0
+    assert L.tof_ctx_bytes(None) == 0
     assert L.tof_set_option(None, tof.OPT_FUSE_YZ, 1) == -1
     assert L.tof_profile_kernel(None, 0, None) == b""
     L.tof_destroy(None)
@@ -94,3 +97,28 @@ def test_bad_newell_arguments_give_nan():
     assert np.isnan(tof.newell_host(6, (0, 0, 0), (1, 1, 1)))
     assert np.isnan(tof.newell_host(0, (-1, 0, 0), (1, 1, 1)))
     assert np.isnan(tof.newell_host(0, (0, 0, 0), (0, 1, 1)))
+
+
+def test_workspace_bytes_before_create():
+    """tof_workspace_bytes sizes a context from the grid alone (host
+    arithmetic, no device): at 256 x 256 x 128 in FP32 (padded 512 x 512 x
+    256, hx = 257) the x-y transformed tensor, the spectra and the three pass
+    workspaces dominate; FP64 doubles them."""
+    b32 = tof.workspace_bytes((256, 256, 128), (1, 1, 1), "f32")
+    b64 = tof.workspace_bytes((256, 256, 128), (1, 1, 1), "f64")
+    hx, hkz = 257, 129
+    ky_pitch = (257 + 15) // 16 * 16
+    spec = 4 * 6 * hx * hkz * ky_pitch
+    kt = 4 * 6 * hx * 128 * 512
+    A = C = 8 * 3 * hx * 128 * 256
+    B = 8 * 3 * hx * 128 * 512
+    big = spec + kt + A + B + C
+    assert big <= b32 <= big + 200_000
+    assert 2 * big <= b64 <= 2 * big + 200_000
+    # explicit padded lengths change the spectra and B
+    assert tof.workspace_bytes((256, 256, 128), (1, 1, 1), "f32", L=(512, 512, 512)) > b32
+    # invalid grids give 0 and a message
+    with pytest.raises(tof.TofError):
+        tof.workspace_bytes((0, 4, 4), (1, 1, 1))
+    with pytest.raises(tof.TofError):
+        tof.workspace_bytes((11, 4, 4), (1, 1, 1), L=(22, 8, 8))

@@ -174,3 +174,36 @@ def test_tuned_schedules_give_the_same_result(torch):
         e.close()
         assert abs(J - J0.item()) <= 1e-12 * abs(J0.item())
         assert np.abs(g - g0).max() <= 1e-12 * np.abs(g0).max()
+
+
+def c5_reference(cache):
+    """Oracle J and full gradient of all 64 designs of the batch (FP64)."""
+    if "c5" not in cache:
+        import time
+        t0 = time.perf_counter()
+        cache["c5"] = [oracle.objective_and_grad(w)[:2] for w in wl.config5()]
+        say(f"oracle: 64 designs in {time.perf_counter() - t0:.1f} s")
+    return cache["c5"]
+
+
+@pytest.mark.gpu
+def test_whole_batch_with_tuned_schedules_matches_oracle(torch, oracle_cache):
+    """All 64 designs, with the schedules the tuner picks (as the benchmark
+    runs them), evaluated by one graph replay in FP32: J and the whole
+    gradient of every design against the oracle at 1e-5."""
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = wl.config5()
+    sched = [autotune.tune_schedule(w, "f32", evals=2)[0] for w in ws]
+    b = DesignBatch(ws, "f32", [L for L, _ in sched], streams=4, passes=[p for _, p in sched])
+    b.capture()
+    b.replay()
+    got = b.results()
+    b.close()
+    ref = c5_reference(oracle_cache)
+    worst = 0.0
+    for i, (w, (J, g), (Jr, gr)) in enumerate(zip(ws, got, ref)):
+        eJ = abs(J - Jr) / abs(Jr)
+        eg = float(np.abs(g.astype(np.float64) - gr).max() / np.abs(gr).max())
+        worst = max(worst, eJ, eg)
+        assert eJ <= 1e-5 and eg <= 1e-5, (i, w.name, sched[i], eJ, eg)
+    say(f"batch: worst relative error over 64 designs {worst:.2e}")

@@ -2,6 +2,7 @@
 hand-written adjoint) and of the precision form (the projected-gradient loop
 in FP32 with its error against FP64 and the oracle along the iterates)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -108,15 +109,14 @@ def test_c3_precision_loop(torch):
     """200 projected-gradient iterations in FP32 on 256 x 256 x 128 (rho
     clamped to [0, 1]); every 20 iterations the FP32 gradient is compared with
     the plain FP64 GPU path on the same iterate, and at iterations 0, 100 and
-    200 both are compared with the oracle (J, and the gradient on the top
-    design layer under the sensor plus random cells).
+    200 both are compared with the oracle's J and whole gradient on that
+    iterate.
 
-    Bar: FP64 within 1e-10 of the oracle; FP32 within 1e-5 relative on J and
-    on the gradient at the random start (as in the parity tests), and, along
-    the trajectory, FP32 gradient errors within 1e-5 of the starting gradient
-    scale.  The error relative to the iterate's own gradient is reported: it
-    grows as the optimization drives Hz - t and with it the gradient towards
-    zero (the FP32 field error stays ~1e-7 |H| while |Hz - t| shrinks)."""
+    Bar, at every compared iterate and relative to that iterate's own
+    gradient (max |g - g_ref| / max |g_ref|): FP64 within 1e-10 of the
+    oracle; FP32 within 1e-5 of the FP64 path and of the oracle, on J and on
+    the gradient.  The error against the starting gradient scale is reported
+    as well."""
     from paper_1707_09898_amd import tof
 
     w = wl.config3()
@@ -126,9 +126,6 @@ def test_c3_precision_loop(torch):
     g32 = torch.empty_like(rho)
     J32 = torch.empty(1, dtype=torch.float64, device="cuda")
     table = oracle.table_for(w)
-    top = w.design[5] - 1
-    cells = [(top, y, x) for y in range(94, 162, 6) for x in range(94, 162, 6)]
-    cells += random_design_cells(w, 32, 3)
     report = []
     Js = []
     gscale0 = None
@@ -149,23 +146,19 @@ def test_c3_precision_loop(torch):
                    "grad_err_vs_start_scale": e_abs / gscale0}
             if k in (0, 100, 200):
                 rho_np = r64.cpu().numpy()
-                Jr, gr = sampled_reference(w, cells, rho_np, table)
-                s32 = np.array([a32[c] for c in cells])
-                s64 = np.array([a64[c] for c in cells])
+                t0 = time.perf_counter()
+                Jr, gr, _ = oracle.objective_and_grad(w, rho_np, table)
+                gs = float(np.abs(gr).max())
                 row.update({"relJ_32_vs_oracle": abs(J32.item() - Jr) / abs(Jr),
                             "relJ_64_vs_oracle": abs(J64.item() - Jr) / abs(Jr),
-                            "relgrad_32_vs_oracle": float(np.abs(s32 - gr).max() / np.abs(gr).max()),
-                            "relgrad_64_vs_oracle": float(np.abs(s64 - gr).max() / np.abs(gr).max())})
-                assert row["relJ_64_vs_oracle"] <= 1e-10 and row["relgrad_64_vs_oracle"] <= 1e-10
-                assert row["relJ_32_vs_oracle"] <= 1e-5
-                assert float(np.abs(s32 - gr).max()) <= 1e-5 * gscale0
-                if k == 0:
-                    assert row["relgrad_32_vs_oracle"] <= 1e-5
+                            "relgrad_32_vs_oracle": float(np.abs(a32 - gr).max()) / gs,
+                            "relgrad_64_vs_oracle": float(np.abs(a64 - gr).max()) / gs,
+                            "oracle_s": time.perf_counter() - t0})
+                assert row["relJ_64_vs_oracle"] <= 1e-10 and row["relgrad_64_vs_oracle"] <= 1e-10, row
+                assert row["relJ_32_vs_oracle"] <= 1e-5 and row["relgrad_32_vs_oracle"] <= 1e-5, row
             say("  " + " ".join(f"{kk}={v:.3e}" if isinstance(v, float) else f"{kk}={v}" for kk, v in row.items()))
             report.append(row)
-            assert e_j <= 1e-5 and e_abs <= 1e-5 * gscale0
-            if k == 0:
-                assert e_g <= 1e-5
+            assert e_j <= 1e-5 and e_g <= 1e-5, row
         Js.append(J32.item())
         e32.project_step(rho, g32, 0.05)
     # the loop makes progress and keeps rho in [0, 1]

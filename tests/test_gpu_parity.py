@@ -1,13 +1,15 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle, element
 by element on seeded inputs (small and ragged sizes that span several tiles),
-and on sampled outputs at the full 256 x 256 x 128 size in the launch
-configuration the benchmark times.
+and on the whole gradient at the full 256 x 256 x 128 size on every pass
+choice (the fused one in the launch configuration the benchmark times);
+boundary behaviour (validation, the setup self-check, workspace sizing).
 
 Tolerances (normwise, max|x - ref| / max|ref|): 1e-10 in FP64 and 1e-5 in
 FP32, the accuracy targets of the gradient engine; J relative to |J|.
 """
 import dataclasses
 import sys
+import time
 
 import ctypes
 
@@ -98,6 +100,11 @@ def test_gpu_tensor_matches_oracle(torch, n, h):
         assert np.abs(N[c] - ref[c]).max() <= 1e-15 * scale, c
 
 
+def masked(w, seed, fraction=0.6):
+    """w with a seeded random design mask."""
+    return dataclasses.replace(w, mask=wl.random_mask(seed, w.n, fraction))
+
+
 # ---------------------------------------------------------------- field
 FIELD_CASES = [
     ("c1", lambda: wl.config1()),
@@ -107,6 +114,8 @@ FIELD_CASES = [
     ("nonsmooth", lambda: wl.small_random(24, n=(11, 13, 6), h=(1.0, 1.0, 1.0))),  # 2n = 22, 26: L = 24, 28
     # two design rows, Ly = 32: the few-source-row paths
     ("thin_design", lambda: wl.small_random(25, n=(11, 16, 9), design=(1, 10, 0, 16, 2, 4))),
+    # a random design mask inside the box (chi = box and mask)
+    ("masked", lambda: masked(wl.small_random(27, n=(12, 11, 10), design=(1, 11, 0, 11, 0, 7)), 27)),
 ]
 
 
@@ -154,6 +163,11 @@ GRAD_CASES = [
     # two design layers and Lx = Ly = 32: on the fused path the adjoint's
     # target has few rows (the gather), so J is formed by a kernel of its own
     ("thin_design_grad", lambda: wl.small_random(26, n=(16, 16, 9), design=(0, 16, 0, 16, 2, 4))),
+    # random design masks: the uniform-M0 Hz objective (Ly = 32: fused kernels) and
+    # varying M0 with a vector target (three components through the masked epilogue)
+    ("masked_gradxy", lambda: masked(wl.small_random(44, n=(16, 16, 11), design=(0, 16, 0, 16, 0, 7)), 44)),
+    ("masked_vector", lambda: masked(wl.small_random(45, n=(10, 12, 9), j_kind=wl.J_MEAN_SQ_H_TARGET,
+                                                     varying_m0=True), 45, 0.5)),
 ]
 
 
@@ -171,8 +185,8 @@ def test_gpu_objective_and_grad_match_oracle(torch, name, make, dtype, path):
     Jr, gr, _ = cached(("grad", name), lambda: oracle.objective_and_grad(w))
     assert abs(J - Jr) <= TOL[dtype] * abs(Jr), (J, Jr)
     assert rel_inf(g, gr) <= TOL[dtype], rel_inf(g, gr)
-    # zero outside the design region
-    chi = oracle.box_mask(w.n, w.design)
+    # zero outside the design region (box and mask)
+    chi = oracle.design_chi(w)
     assert np.all(g[chi == 0] == 0.0)
 
 
@@ -251,19 +265,50 @@ def test_gpu_is_deterministic_and_stream_safe(torch):
     assert torch.equal(g1, g2) and torch.equal(J1, J2)
 
 
-def test_gpu_project_step(torch):
-    w = wl.small_random(42, n=(10, 9, 8))
-    e = tof().engine_for(w, "f64")
-    rho = dev(torch, w.rho, torch.float64)
+STEP_TOL = {"f64": 1e-15, "f32": 2.5e-7}   # rho in [0, 1]: a few ulp of 1
+
+
+@pytest.mark.parametrize("with_mask", [False, True])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gpu_project_step_matches_oracle(torch, dtype, with_mask):
+    """tof_project_step against the oracle's projected step, on the same
+    density and gradient (the gradient of the problem itself), with and
+    without a design mask; cells outside chi keep their value exactly."""
+    w = wl.small_random(42, n=(10, 9, 8), design=(1, 9, 0, 8, 0, 6))
+    if with_mask:
+        w = masked(w, 42)
+    say("project step", dtype, with_mask)
+    e = tof().engine_for(w, dtype)
+    rho = dev(torch, w.rho, e.dtype)
+    rho0 = host(rho)
     J, g = e.objective_and_grad(rho)
     gh = host(g)
     e.project_step(rho, g, 0.05)
     torch.cuda.synchronize()
-    x0, x1, y0, y1, z0, z1 = w.design
-    want = w.rho.copy()
-    gm = np.abs(gh[z0:z1, y0:y1, x0:x1]).max()
-    want[z0:z1, y0:y1, x0:x1] = np.clip(w.rho[z0:z1, y0:y1, x0:x1] - 0.05 * gh[z0:z1, y0:y1, x0:x1] / gm, 0, 1)
-    np.testing.assert_allclose(host(rho), want, rtol=0, atol=1e-15)
+    got = host(rho)
+    want = oracle.project_step(w, rho0, gh, 0.05)
+    assert np.abs(got - want).max() <= STEP_TOL[dtype]
+    chi = oracle.design_chi(w)
+    assert np.array_equal(got[chi == 0], rho0[chi == 0])
+    # clamping at both bounds: a large step drives cells to 0 and to 1
+    e.project_step(rho, g, 5.0)
+    torch.cuda.synchronize()
+    got2 = host(rho)
+    want2 = oracle.project_step(w, got, gh, 5.0)
+    assert np.abs(got2 - want2).max() <= STEP_TOL[dtype]
+    assert np.any(got2[chi == 1] == 0.0) and np.any(got2[chi == 1] == 1.0)
+
+
+def test_gpu_project_step_zero_gradient(torch):
+    """G = 0 leaves rho unchanged, also values outside [0, 1]."""
+    w = wl.small_random(46, n=(8, 7, 6))
+    e = tof().engine_for(w, "f64")
+    r = w.rho.copy()
+    r[0, 0, 0], r[1, 2, 3] = 1.5, -0.25
+    rho = dev(torch, r, torch.float64)
+    e.project_step(rho, torch.zeros_like(rho), 0.3)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(rho), r)
 
 
 def test_gpu_zero_density(torch):
@@ -276,40 +321,117 @@ def test_gpu_zero_density(torch):
     assert torch.count_nonzero(g).item() == 0
 
 
-# ---------------------------------------------------------------- full size, sampled
-def sampled_reference(w, cells):
-    """Oracle J, g on the objective box, and the gradient at sampled cells."""
-    table = oracle.table_for(w)
-    H = oracle.forward_field(w, table=table)
-    J, g = oracle.objective(w, H)
-    ob = oracle.objective_box(w)
-    jm = oracle.objective_mask(w)
-    out = []
-    for (z, y, x) in cells:
-        A = oracle.field(w.n, w.h, g, ob, (x, x + 1, y, y + 1, z, z + 1), jm, oracle.m0_mask(w), table)
-        out.append(oracle.gradient_from_adjoint(w, A)[z, y, x])
-    return J, np.array(out)
+# ---------------------------------------------------------------- full size
+def c3_reference(cache):
+    """The oracle's J and full gradient of the 256 x 256 x 128 workload
+    (direct sums over every design cell; computed once per test run)."""
+    if "c3" not in cache:
+        w = wl.config3()
+        say(f"oracle: full 256x256x128 gradient on {oracle.num_threads()} threads ...")
+        t0 = time.perf_counter()
+        J, g, _ = oracle.objective_and_grad(w)
+        say(f"  oracle done in {time.perf_counter() - t0:.1f} s")
+        cache["c3"] = (J, g)
+    return cache["c3"]
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_gpu_full_size_256x256x128_sampled(torch, dtype):
-    """The benchmark workload (256 x 256 x 128, padded 512 x 512 x 256) in
-    the benchmark's launch configuration: J exactly, and the gradient on the
-    whole top design layer under the sensor (where it is largest) plus random
-    design cells, against the oracle's direct sums."""
+def test_gpu_full_size_256x256x128(torch, oracle_cache, dtype, path):
+    """The benchmark workload (256 x 256 x 128, padded 512 x 512 x 256) on
+    each pass choice (fused: the benchmark's launch configuration; the direct
+    z sum in its own pass; FFTs along z with Lz = 256): J and the whole
+    gradient array against the oracle's direct sums."""
     w = wl.config3()
-    say("full size", dtype)
-    e = tof().engine_for(w, dtype)
+    say("full size", dtype, path)
+    e = engine_on_path(w, dtype, path)
     assert e.padded_lengths() == (512, 512, 256)
     J, g = e.objective_and_grad(dev(torch, w.rho, e.dtype))
     torch.cuda.synchronize()
     g = host(g)
-    rng = np.random.default_rng(3)
-    top = w.design[5] - 1
-    cells = [(top, y, x) for y in range(94, 162, 4) for x in range(94, 162, 4)]
-    cells += [(int(rng.integers(0, 124)), int(rng.integers(0, 256)), int(rng.integers(0, 256))) for _ in range(64)]
-    Jr, gr = sampled_reference(w, cells)
-    got = np.array([g[c] for c in cells])
+    e.close()
+    Jr, gr = c3_reference(oracle_cache)
+    err = rel_inf(g, gr)
+    say(f"  rel err J {abs(float(J.item()) - Jr) / abs(Jr):.2e}, grad {err:.2e}")
     assert abs(float(J.item()) - Jr) <= TOL[dtype] * abs(Jr)
-    assert np.abs(got - gr).max() <= TOL[dtype] * np.abs(gr).max()
+    assert err <= TOL[dtype]
     assert np.all(g[124:] == 0.0)
+
+
+# ---------------------------------------------------------------- boundary
+def test_gpu_validate_rejects_non_finite_inputs(torch):
+    """With validation on, NaN or infinite inputs return TOF_ERR_INVALID
+    before anything else is launched (the outputs stay untouched); finite
+    inputs give the same result as without validation."""
+    t = tof()
+    w = wl.small_random(47, n=(12, 10, 9))
+    ev = t.engine_for(w, "f32", validate=True)
+    e = t.engine_for(w, "f32")
+    rho = dev(torch, w.rho, torch.float32)
+    Jv, gv = ev.objective_and_grad(rho)
+    J, g = e.objective_and_grad(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(gv, g) and torch.equal(Jv, J)
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        r = rho.clone()
+        r[3, 4, 5] = bad
+        out = torch.full_like(rho, 7.0)
+        with pytest.raises(t.TofError) as ei:
+            ev.objective_and_grad(r, out)
+        assert ei.value.status == -1 and "rho" in str(ei.value)
+        with pytest.raises(t.TofError):
+            ev.field(r)
+        torch.cuda.synchronize()
+        assert torch.all(out == 7.0)
+    gH = torch.zeros((3,) + rho.shape, dtype=torch.float32, device="cuda")
+    gH[1, 2, 3, 4] = float("nan")
+    with pytest.raises(t.TofError) as ei:
+        ev.adjoint(rho, gH)
+    assert "gH" in str(ei.value)
+    # without validation the call goes through (NaN propagates)
+    r = rho.clone()
+    r[3, 4, 5] = float("nan")
+    J2, g2 = e.objective_and_grad(r)
+    torch.cuda.synchronize()
+    assert torch.isnan(J2).any() or torch.isnan(g2).any()
+
+
+def test_gpu_tensor_trace_self_check(torch):
+    """Setup checks max |tr N(k) - delta_k0| < 1e-12; the test hook that adds
+    1e-9 to one tensor entry makes tof_create fail with TOF_ERR_NUMERIC."""
+    t = tof()
+    t.Engine((9, 8, 7), (1.0, 0.8, 1.3), "f64").close()
+    with pytest.raises(t.TofError) as ei:
+        t.Engine((9, 8, 7), (1.0, 0.8, 1.3), "f64", flags=t.GRID_SELFTEST_PERTURB)
+    assert ei.value.status == -5 and "trace" in str(ei.value)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gpu_workspace_bytes_before_create_match_the_context(torch, dtype):
+    t = tof()
+    for n, L in (((256, 256, 128), None), ((13, 10, 7), None), ((16, 16, 9), (32, 32, 32))):
+        want = t.workspace_bytes(n, (1.0, 1.0, 1.0), dtype, L)
+        e = t.Engine(n, (1.0, 1.0, 1.0), dtype, L=L)
+        assert e.ctx_bytes() == want, (n, L)
+        e.close()
+
+
+def test_gpu_device_target_field_equals_host(torch):
+    """Kind 3 with H* given as a device pointer gives the same result, bit
+    for bit, as with H* from host memory."""
+    t = tof()
+    w = wl.small_random(48, n=(10, 11, 12), j_kind=wl.J_MEAN_SQ_H_TARGET, varying_m0=True)
+    e = t.engine_for(w, "f64")
+    rho = dev(torch, w.rho, torch.float64)
+    J1, g1 = e.objective_and_grad(rho)
+    J1, g1 = J1.clone(), g1.clone()
+    e.set_objective(w.j_kind, w.sensor, w.j_target, w.j_lambda, dev(torch, w.h_target, torch.float64))
+    J2, g2 = e.objective_and_grad(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(J1, J2) and torch.equal(g1, g2)
+    # a rejected objective (sensor outside the grid) leaves the previous one in place
+    with pytest.raises(t.TofError):
+        e.set_objective(w.j_kind, (0, 99, 0, 2, 0, 1), 0.0, 0.0, w.h_target)
+    J3, g3 = e.objective_and_grad(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(J1, J3) and torch.equal(g1, g3)
