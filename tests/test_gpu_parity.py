@@ -290,11 +290,14 @@ def test_gpu_project_step_matches_oracle(torch, dtype, with_mask):
     assert np.abs(got - want).max() <= STEP_TOL[dtype]
     chi = oracle.design_chi(w)
     assert np.array_equal(got[chi == 0], rho0[chi == 0])
-    # clamping at both bounds: a large step drives cells to 0 and to 1
-    e.project_step(rho, g, 5.0)
+    # clamping at both bounds: a large step along a gradient of both signs
+    # drives cells to 0 and to 1
+    flip = np.where(np.random.default_rng(7).random(gh.shape) < 0.5, -1.0, 1.0)
+    gmix = dev(torch, gh * flip, e.dtype)
+    e.project_step(rho, gmix, 5.0)
     torch.cuda.synchronize()
     got2 = host(rho)
-    want2 = oracle.project_step(w, got, gh, 5.0)
+    want2 = oracle.project_step(w, got, host(gmix), 5.0)
     assert np.abs(got2 - want2).max() <= STEP_TOL[dtype]
     assert np.any(got2[chi == 1] == 0.0) and np.any(got2[chi == 1] == 1.0)
 
