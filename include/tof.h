@@ -210,6 +210,27 @@ tof_status tof_adjoint(tof_ctx *ctx, const void *rho, const void *gH, void *grad
 tof_status tof_project_step(tof_ctx *ctx, void *rho, const void *grad, double alpha, void *stream);
 
 /*
+ * tof_project_step_static -- tof_project_step without a context, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): it allocates nothing and
+ * launches the same two kernels.  Their scratch (the partial maxima of the
+ * first launch, at most 2048 doubles = 16 KiB) is a static device array of
+ * the library, one per GPU, held until the process ends; every entry the
+ * second launch reads is written by the first, so nothing needs clearing.
+ * All calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams, other threads) race; serialize them.
+ *  grid:   only nx, ny, nz (each in [1, 512]) and dtype are read.
+ *  design: index box of design cells (NULL = whole grid); mask: optional
+ *          device uint8 [nz][ny][nx], chi = box && mask != 0.
+ *  rho (updated in place), grad: device [nz][ny][nx] of the dtype; alpha >= 0.
+ * Same update as tof_project_step.  Errors: TOF_ERR_INVALID (null pointers,
+ * sizes beyond 512 per axis, bad box or alpha), TOF_ERR_HIP.  The message is
+ * the thread's (tof_last_error(NULL)).
+ */
+tof_status tof_project_step_static(const tof_grid *grid, const tof_box *design, const uint8_t *mask, void *rho,
+                                   const void *grad, double alpha, void *stream);
+
+/*
  * tof_tensor -- the real-space tensor as computed on the GPU (for checks):
  * N_c(k) for offsets 0 <= k_a < n_a, device double [6][nz][ny][nx],
  * components xx, yy, zz, xy, xz, yz; other offsets follow by parity (the

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -758,6 +759,39 @@ tof_status check_finite_any(tof_ctx *ctx, hipStream_t st, const void *a, long lo
     return ctx->f64 ? check_finite<double>(ctx, st, a, n, what) : check_finite<float>(ctx, st, a, n, what);
 }
 
+// Scratch of tof_project_step_static: the partial maxima of its first
+// launch.  Every GPU the library runs on holds its own copy of this array
+// until the process ends; host code never uses its name as an address, only
+// the per-device pointer from hipGetSymbolAddress (static_scratch_ptr).
+static __device__ __align__(256) double scratch[kStepMaxBlocks];
+
+constexpr int kMaxDevices = 64;
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept; nullptr on failure (msg says why).
+double *static_scratch_ptr(std::string &msg)
+{
+    static std::mutex mu;
+    static void *ptrs[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        msg = std::string("hipGetDevice: ") + (e != hipSuccess ? hipGetErrorString(e) : "device index out of range");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptrs[dev] = p;
+    }
+    return (double *)ptrs[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -968,6 +1002,31 @@ tof_status tof_project_step(tof_ctx *ctx, void *rho, const void *grad, double al
     else
         HIP_TRY(ctx, launch_project_step<float>(st, (float *)rho, (const float *)grad, ctx->mask, ctx->nx, ctx->ny,
                                                 ctx->nz, ctx->design, alpha, part));
+    return TOF_OK;
+}
+
+tof_status tof_project_step_static(const tof_grid *grid, const tof_box *design, const uint8_t *mask, void *rho,
+                                   const void *grad, double alpha, void *stream)
+{
+    if (!grid) return fail(nullptr, TOF_ERR_INVALID, "grid is null");
+    const tof_grid &g = *grid;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nx > kMaxL / 2 || g.ny > kMaxL / 2 || g.nz > kMaxL / 2)
+        return fail(nullptr, TOF_ERR_INVALID, "grid sizes must be in [1, 512] (the largest grid the static scratch serves)");
+    if (g.dtype != TOF_F32 && g.dtype != TOF_F64) return fail(nullptr, TOF_ERR_INVALID, "dtype must be TOF_F32 or TOF_F64");
+    if (!rho || !grad) return fail(nullptr, TOF_ERR_INVALID, "rho and grad must be non-null");
+    if (!std::isfinite(alpha) || alpha < 0) return fail(nullptr, TOF_ERR_INVALID, "alpha must be finite and >= 0");
+    const Box d = design ? to_box(*design) : Box{0, g.nx, 0, g.ny, 0, g.nz};
+    if (!box_ok(d, g.nx, g.ny, g.nz)) return fail(nullptr, TOF_ERR_INVALID, "design box outside the grid or empty");
+    std::string msg;
+    double *part = static_scratch_ptr(msg);
+    if (!part) return fail(nullptr, TOF_ERR_HIP, msg);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = g.dtype == TOF_F64
+                       ? launch_project_step<double>(st, (double *)rho, (const double *)grad, mask, g.nx, g.ny, g.nz, d,
+                                                     alpha, part)
+                       : launch_project_step<float>(st, (float *)rho, (const float *)grad, mask, g.nx, g.ny, g.nz, d,
+                                                    alpha, part);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "tof_project_step_static");
     return TOF_OK;
 }
 

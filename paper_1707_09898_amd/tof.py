@@ -21,7 +21,7 @@ STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TO
           -4: "TOF_ERR_HIP", -5: "TOF_ERR_NUMERIC", -6: "TOF_ERR_STATE"}
 
 EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "tof_field",
-           "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
+           "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_project_step_static", "tof_tensor",
            "tof_padded_lengths", "tof_workspace_bytes", "tof_ctx_bytes", "tof_last_error", "tof_dd_newell_host",
            "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option"]
 
@@ -77,6 +77,7 @@ def lib():
         L.tof_objective_and_grad.argtypes = [vp, vp, vp, vp, vp]
         L.tof_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.tof_project_step.argtypes = [vp, vp, vp, dbl, vp]
+        L.tof_project_step_static.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(BoxC), vp, vp, vp, dbl, vp]
         L.tof_tensor.argtypes = [vp, vp, vp]
         L.tof_padded_lengths.argtypes = [vp, ctypes.POINTER(i32)]
         L.tof_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
@@ -93,8 +94,8 @@ def lib():
         L.tof_profile_kernel.restype = ctypes.c_char_p
         L.tof_set_option.argtypes = [vp, i32, i32]
         for name in ("tof_create", "tof_set_design", "tof_set_objective", "tof_field",
-                     "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_tensor",
-                     "tof_padded_lengths", "tof_profile_enable", "tof_profile_read", "tof_set_option"):
+                     "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_project_step_static",
+                     "tof_tensor", "tof_padded_lengths", "tof_profile_enable", "tof_profile_read", "tof_set_option"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -267,6 +268,28 @@ def workspace_bytes(n, h, dtype: str = "f32", L=None) -> int:
     if b == 0:
         raise TofError(-1, lib().tof_last_error(None).decode())
     return b
+
+
+def project_step_static(rho, grad, alpha: float, design=None, mask=None, stream=None):
+    """tof_project_step_static: the projected step with no context and no
+    allocation (rho [nz][ny][nx] is updated in place)."""
+    import torch
+    if rho.dtype not in (torch.float32, torch.float64) or rho.device.type != "cuda" or not rho.is_contiguous() \
+            or rho.dim() != 3 or grad.shape != rho.shape or grad.dtype != rho.dtype or not grad.is_contiguous():
+        raise ValueError("rho and grad must be contiguous 3-d cuda tensors of one float dtype")
+    nz, ny, nx = (int(v) for v in rho.shape)
+    g = make_grid((nx, ny, nz), (1.0, 1.0, 1.0), "f32" if rho.dtype == torch.float32 else "f64")
+    bx = ctypes.byref(_box(design)) if design is not None else None
+    mk = None
+    if mask is not None:
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != tuple(rho.shape) or not mask.is_contiguous():
+            raise ValueError("mask must be a contiguous uint8 tensor shaped like rho")
+        mk = ctypes.c_void_p(mask.data_ptr())
+    st = lib().tof_project_step_static(ctypes.byref(g), bx, mk, ctypes.c_void_p(rho.data_ptr()),
+                                       ctypes.c_void_p(grad.data_ptr()), float(alpha), _stream_ptr(stream))
+    if st != 0:
+        raise TofError(st, lib().tof_last_error(None).decode())
+    return rho
 
 
 def engine_for(w, dtype: str = "f32", stream=None, L=None, validate: bool = False) -> Engine:
