@@ -2,12 +2,20 @@
 
 One step = one full gradient evaluation (forward convolution on the cells the
 objective reads, J in FP64, adjoint convolution onto the design cells,
-dJ/drho) through the C ABI, with rho already resident in HBM.
+dJ/drho) through the C ABI, with rho already resident in HBM.  The timed
+path is the sensor-pruned one (x transforms, then the y transforms fused
+with a direct sum along z against the x-y transformed tensor, since the
+objective reads one z layer); its own byte model is the sum of the passes'
+algorithmic bytes.  The five-pass FFT pipeline (FFTs along all three axes,
+the tensor product per frequency) is measured beside it, as the field of the
+whole grid and as the gradient, against the full-field byte model.
 
-Prints one JSON line: the FP32 rate (the value), the plain FP64 GPU rate and
-their ratio, the dominant kernel against the HBM roofline (per-launch HIP
-events on the launch stream, algorithmic bytes from the pass sizes), and the
-CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: the FP32 rate (the value: the median of 5 timed loops
+of K steps each), the plain FP64 GPU rate and their ratio, the dominant
+kernel and the whole evaluation against the HBM roofline (per-launch HIP
+events on the launch stream, algorithmic bytes from the pass sizes), the
+full-field pipeline, the 64-design batch, and the CPU oracle timed on whole
+evaluations of the same workload.
 """
 import argparse
 import json
@@ -25,53 +33,148 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gradient_eval_256x256x128_kernels.md")
 
 
+def per_field_words(w, L):
+    """Words one axis sweep of the five-pass pipeline moves per field: rho or
+    the output (n), the x-pass output written and read (4 hx ny nz), the
+    y-pass output written and read (4 hx Ly nz)."""
+    nx, ny, nz = w.n
+    Lx, Ly, Lz = L
+    hx = Lx // 2 + 1
+    return nx * ny * nz + 4 * hx * ny * nz + 4 * hx * Ly * nz
+
+
+def spectrum_words(L):
+    Lx, Ly, Lz = L
+    return (Lx // 2 + 1) * (Ly // 2 + 1) * (Lz // 2 + 1)
+
+
 def model_bytes_per_eval(w, wsize, L):
     """Full-field pass model of one gradient evaluation (two scalar
     convolutions over the whole padded box, zero padding never stored, the
     tensor spectrum octant read once per convolution)."""
     nx, ny, nz = w.n
-    Lx, Ly, Lz = L
-    hx = Lx // 2 + 1
-    per_field = nx * ny * nz + 4 * hx * ny * nz + 4 * hx * Ly * nz
-    K = hx * (Ly // 2 + 1) * (Lz // 2 + 1)
-    return wsize * (2 * 2 * per_field + 2 * K + nx * ny * nz)
+    return wsize * (2 * 2 * per_field_words(w, L) + 2 * spectrum_words(L) + nx * ny * nz)
 
 
-def time_steps(torch, e, rho, grad, J, steps):
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
-        e.objective_and_grad(rho, grad, J)
-    t1.record()
-    torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps
+def model_bytes_per_field(w, wsize, L):
+    """The same model for one field H_z = -N (*) M (one scalar convolution)."""
+    return wsize * (2 * per_field_words(w, L) + spectrum_words(L))
 
 
-def cpu_baseline(w, layers=16):
-    """The oracle (direct sums, FP64) on the host cores: the full forward
-    field on the objective's cells, J and dJ/dH, and the adjoint on `layers`
-    of the design layers; the adjoint time is scaled to all design layers
-    (its cost is linear in the number of target cells)."""
+def timed_loops(torch, fn, steps, repeats):
+    """ms per call of fn over `repeats` timed loops of exactly `steps` calls,
+    each bracketed by device synchronizations (HIP events on the current stream)."""
+    out = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        out.append(t0.elapsed_time(t1) / steps)
+    return out
+
+
+def median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, repeats):
+    """The oracle (direct sums, FP64, OpenMP over the host cores) on whole
+    evaluations of the workload: the forward field on the objective's cells,
+    J and dJ/dH, the adjoint on every design cell and dJ/drho; the tensor
+    table is setup and not timed.  The median over `repeats` evaluations."""
     import oracle
     table = oracle.table_for(w)        # setup, not timed
-    t0 = time.perf_counter()
-    H = oracle.forward_field(w, table=table)
-    J, g = oracle.objective(w, H)
-    t1 = time.perf_counter()
-    x0, x1, y0, y1, z0, z1 = w.design
-    sub = (x0, x1, y0, y1, z1 - layers, z1)
-    A = oracle.field(w.n, w.h, g, oracle.objective_box(w), sub, oracle.objective_mask(w),
-                     oracle.m0_mask(w), table)
-    oracle.gradient_from_adjoint(w, A)
-    t2 = time.perf_counter()
-    per_eval = (t1 - t0) + (t2 - t1) * (z1 - z0) / layers
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.objective_and_grad(w, table=table)
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] oracle evaluation {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    per_eval = median(times)
     return {"value": 1.0 / per_eval, "unit": "gradient evals/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"one evaluation: full forward direct sum on the {w.sensor[1]-w.sensor[0]+2}x"
-                      f"{w.sensor[3]-w.sensor[2]+2} objective cells, adjoint direct sum on {layers} of "
-                      f"{z1 - z0} design layers scaled linearly; FP64; {t2 - t0:.1f} s measured"}
+            "kind": "oracle", "cpu_model": cpu_model(), "seconds_per_eval": times,
+            "sample": f"{repeats} whole evaluations of the same workload (forward direct sum on the "
+                      f"{w.sensor[1]-w.sensor[0]+2}x{w.sensor[3]-w.sensor[2]+2} objective cells, adjoint "
+                      f"direct sum on all {w.design[5] - w.design[4]} design layers), FP64; median"}
+
+
+def full_field_measurement(torch, tof, w, steps, repeats):
+    """The five-pass FFT pipeline at 256 x 256 x 128 FP32: (a) the field H_z
+    of the whole grid (tof_field, FFTs along x, y and z with the tensor
+    product per frequency), and (b) the gradient with FFTs along z (the
+    direct z sums switched off), each against the full-field byte model,
+    with the dominant kernel of the field against the HBM roofline."""
+    e = tof.engine_for(w, "f32")
+    L = e.padded_lengths()
+    rho = torch.as_tensor(w.rho, dtype=torch.float32, device="cuda")
+    H = torch.empty((1,) + rho.shape, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        e.field(rho, comps=4, out=H)
+    ms = median(timed_loops(torch, lambda: e.field(rho, comps=4, out=H), steps, repeats))
+    e.profile(True)
+    for _ in range(steps):
+        e.field(rho, comps=4, out=H)
+    prof = e.profile_read()
+    kernels = e.profile_kernels(with_items=True)
+    e.profile(False)
+    slots = [(i, name, t / c, c, by) for i, (name, t, c, by) in enumerate(prof) if c > 0]
+    pass_bytes = sum(by for (_, _, _, _, by) in slots)
+    dom = max(slots, key=lambda s: s[2])
+    model_f = model_bytes_per_field(w, 4, L)
+    field = {"what": "tof_field, Hz on all 256x256x128 cells from the 124 design layers (five passes: x R2C, "
+                     "y FFT, z FFT + tensor product + inverse z, inverse y, inverse x C2R)",
+             "ms_per_field": ms, "fields_per_s": 1000.0 / ms,
+             "model_bytes": model_f, "model_GBps": model_f / (ms * 1e-3) / 1e9,
+             "model_frac": model_f / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "pass_bytes": pass_bytes, "pass_GBps": pass_bytes / (ms * 1e-3) / 1e9,
+             "pass_frac": pass_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "per_kernel_us": {f"{name}:{kernels[i][0]}": round(avg * 1e3, 2) for (i, name, avg, _, _) in slots},
+             "dominant_kernel": {"kernel": kernels[dom[0]][0], "slot": dom[1], "avg_launch_us": dom[2] * 1e3,
+                                 "bytes_per_launch": dom[4],
+                                 "achieved_GBps": dom[4] / (dom[2] * 1e-3) / 1e9,
+                                 "frac": dom[4] / (dom[2] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    # the gradient through the same pipeline (z FFTs instead of the direct sums)
+    grad = torch.empty_like(rho)
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    for opt in (tof.OPT_ZSUM, tof.OPT_FUSE_YZ):
+        e.set_option(opt, 0)
+    for _ in range(3):
+        e.objective_and_grad(rho, grad, J)
+    msg = median(timed_loops(torch, lambda: e.objective_and_grad(rho, grad, J), steps, repeats))
+    e.profile(True)
+    for _ in range(steps):
+        e.objective_and_grad(rho, grad, J)
+    prof = e.profile_read()
+    e.profile(False)
+    gbytes = sum(by for (_, _, c, by) in prof if c > 0)
+    model_g = model_bytes_per_eval(w, 4, L)
+    gradient = {"what": "tof_objective_and_grad with FFTs along z (direct z sums off)",
+                "ms_per_eval": msg, "evals_per_s": 1000.0 / msg,
+                "model_bytes": model_g, "model_GBps": model_g / (msg * 1e-3) / 1e9,
+                "model_frac": model_g / (msg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "pass_bytes": gbytes, "pass_GBps": gbytes / (msg * 1e-3) / 1e9,
+                "pass_frac": gbytes / (msg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    e.close()
+    print(f"[bench] full-field pipeline: field {ms:.4f} ms ({field['model_frac']:.2f} of peak on the model), "
+          f"gradient {msg:.4f} ms ({gradient['model_frac']:.2f})", file=sys.stderr, flush=True)
+    return {"field": field, "gradient": gradient}
 
 
 def batch_measurement(torch, wl, args):
@@ -131,6 +234,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--f64-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-repeats", type=int, default=3, help="whole oracle evaluations timed (median)")
+    ap.add_argument("--repeats", type=int, default=5, help="timed loops of --steps steps (median)")
+    ap.add_argument("--no-full-field", action="store_true", help="skip the five-pass pipeline measurement")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch measurement")
     ap.add_argument("--no-paths", action="store_true", help="skip timing the unfused pass choices")
@@ -171,7 +277,8 @@ def main():
         J = torch.empty(1, dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             e.objective_and_grad(rho, grad, J)
-        ms = time_steps(torch, e, rho, grad, J, steps)
+        loops = timed_loops(torch, lambda: e.objective_and_grad(rho, grad, J), steps, args.repeats)
+        ms = median(loops)
         J_main = float(J.item())
         grad_main = grad.double()   # the timed path's gradient, for the precision report
         # per-launch timing in a second pass over the same number of steps
@@ -190,10 +297,12 @@ def main():
                 e.set_option(tof.OPT_FUSE_OBJECTIVE, fo)
                 for _ in range(3):
                     e.objective_and_grad(rho, grad, J)
-                paths[name] = 1000.0 / time_steps(torch, e, rho, grad, J, max(10, steps // 4))
+                paths[name] = 1000.0 / median(timed_loops(torch, lambda: e.objective_and_grad(rho, grad, J),
+                                                          max(10, steps // 4), 3))
             for opt in (tof.OPT_ZSUM, tof.OPT_FUSE_YZ, tof.OPT_FUSE_OBJECTIVE):
                 e.set_option(opt, 1)
-        results[dtype] = {"ms": ms, "prof": prof, "kernels": kernels, "L": L, "J": J_main, "paths": paths}
+        results[dtype] = {"ms": ms, "loops": loops, "prof": prof, "kernels": kernels, "L": L, "J": J_main,
+                          "paths": paths}
         print(f"[bench] {dtype}: {ms:.4f} ms/eval, {1000.0 / ms:.1f} evals/s, J={J_main:.10e}",
               file=sys.stderr, flush=True)
         results[dtype]["grad"] = grad_main
@@ -219,6 +328,15 @@ def main():
         traffic = None
     pass_bytes = sum(by for (_, _, cnt, by) in slots)
     model = model_bytes_per_eval(w, wsize, r32["L"])
+    # measured traffic of the whole evaluation: every timed kernel's counters
+    measured = 0.0
+    for (name, avg, cnt, by) in slots:
+        kname, items = r32["kernels"][tof.PROFILE_NAMES.index(name)]
+        tb, ok = rocprof_summary.lookup(TRAFFIC_SUMMARY, kname, "float", items)
+        if tb is None or not ok:
+            measured = None
+            break
+        measured += tb
     out = {
         "metric": METRIC,
         "value": evals,
@@ -232,9 +350,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded rho ~ U[0,1], p=3, M0=(0,0,1))",
-        "config": {"workload": "c3: 256x256x128 cubic cells padded 512x512x256, design z<124, "
-                               "64x64 sensor plane at z=127, J=mean(Hz-0.2)^2+0.01 mean|grad_xy Hz|^2",
+        "config": {"workload": "c3 sensor-pruned gradient evaluation: 256x256x128 cubic cells padded "
+                               "512x512x256, design z<124, 64x64 sensor plane at z=127, "
+                               "J=mean(Hz-0.2)^2+0.01 mean|grad_xy Hz|^2; x R2C, y FFT fused with a direct z sum "
+                               "against the x-y transformed tensor (one target / source layer), inverse y, "
+                               "inverse x (five kernels per evaluation)",
+                   "form": "sensor-pruned (FFTs along x and y, direct sum along z)",
                    "global_batch": 1, "parallelism": "single GPU"},
+        "repeats": args.repeats,
+        "loops_ms_per_step": r32["loops"],
         "f64_plain": {"value": 1000.0 / results["f64"]["ms"], "ms_per_step": results["f64"]["ms"],
                       "steps": args.f64_steps},
         "speedup_f32_over_f64": results["f64"]["ms"] / r32["ms"],
@@ -246,6 +370,15 @@ def main():
                                   results["f64"]["grad"].abs().max())},
         "bytes_per_eval": {"passes": pass_bytes, "full_field_model": model},
         "effective_GBps": {"passes": pass_bytes * evals / 1e9, "full_field_model": model * evals / 1e9},
+        # the whole evaluation on its own (sensor-pruned) byte model: the sum
+        # of the five kernels' algorithmic bytes per evaluation / the step time
+        "evaluation_roofline": {"bound": "hbm", "bytes_per_eval": pass_bytes,
+                                "achieved": pass_bytes * evals / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": pass_bytes * evals / 1e9 / HBM_PEAK_GBS,
+                                "traffic_per_eval": measured,
+                                "note": "algorithmic bytes of the sensor-pruned passes; traffic = the counters "
+                                        "(copy-calibrated FETCH_SIZE + WRITE_SIZE) of the same five kernels, "
+                                        "null when the sources changed since they were taken"},
         "per_kernel_us": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)][0]}": round(avg * 1e3, 2)
                           for (name, avg, _, _) in slots},
         "paths_f32_evals_per_s": dict({"fused": evals}, **r32["paths"]),
@@ -254,11 +387,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "bytes_per_launch": dom[3], "avg_launch_us": dom[1] * 1e3},
     }
+    if not args.no_full_field:
+        out["full_field_pipeline"] = full_field_measurement(torch, tof, w, max(10, args.steps // 2), args.repeats)
     if not args.no_batch:
         out["c5_batch"] = batch_measurement(torch, wl, args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_repeats)
     print(json.dumps(out), flush=True)
 
 
