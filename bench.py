@@ -177,53 +177,63 @@ def full_field_measurement(torch, tof, w, steps, repeats):
     return {"field": field, "gradient": gradient}
 
 
-def batch_measurement(torch, wl, args):
-    """64 independent designs of uneven size (FP32), schedules (padded
-    lengths and pass structure) chosen by the autotuner, one graph replay per
-    batch evaluation."""
-    from paper_1707_09898_amd import autotune
-    from paper_1707_09898_amd.batch import DesignBatch
-    ws = wl.config5()
-    t0 = time.perf_counter()
-    lengths = passes = None
-    if not args.no_autotune:
-        sched = [autotune.tune_schedule(w, "f32", evals=2)[0] for w in ws]
-        lengths = [L for L, _ in sched]
-        passes = [name for _, name in sched]
-    t1 = time.perf_counter()
-    b = DesignBatch(ws, "f32", lengths, streams=args.batch_streams, passes=passes)
-    nbytes = b.algorithmic_bytes()
+def time_batch(torch, b, replays):
+    """ms per batch evaluation: median of 3 timed loops of graph replays,
+    and the same batch launched eagerly."""
     b.capture()
     for _ in range(3):
         b.replay()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.batch_replays):
-        b.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.batch_replays
-    # eager launches of the same batch, for comparison
+    ms = median(timed_loops(torch, b.replay, replays, 3))
     b.run_eager()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(5):
-        b.run_eager()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_eager = e0.elapsed_time(e1) / 5
+    ms_eager = median(timed_loops(torch, b.run_eager, 5, 3))
+    return ms, ms_eager
+
+
+def batch_measurement(torch, wl, args):
+    """64 independent designs of uneven size (FP32).  The batched form: one
+    launch per pass and kernel instantiation over device tables of the
+    designs (power-of-two padded lengths along x and y), one graph replay per
+    batch evaluation.  For comparison, the designs' own launches spread over
+    streams in one graph, with schedules (padded lengths and pass structure)
+    chosen by the autotuner."""
+    from paper_1707_09898_amd import autotune
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = wl.config5()
     cells = int(sum(int(w.n[0]) * int(w.n[1]) * int(w.n[2]) for w in ws))
-    res = {"designs": len(ws), "cells": cells, "ms_per_batch": ms, "evals_per_s": len(ws) * 1000.0 / ms,
-           "ms_per_batch_eager": ms_eager, "bytes_per_batch": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
-           "streams": args.batch_streams, "autotuned": not args.no_autotune,
-           "autotune_s": round(t1 - t0, 1),
-           "lengths": [list(map(int, e.padded_lengths())) for e in b.engines],
-           "passes": passes}
+    b = DesignBatch(ws, "f32", mode="batched")
+    t0 = time.perf_counter()
+    untuned_ms = b.time_eager()
+    table, tuned_ms, trials = autotune.tune_batch(b)
+    t1 = time.perf_counter()
+    nbytes = b.algorithmic_bytes()
+    launches = b.launches()
+    lengths = [list(map(int, e.padded_lengths())) for e in b.engines]
+    ms, ms_eager = time_batch(torch, b, args.batch_replays)
     b.close()
-    print(f"[bench] c5 batch: {ms:.3f} ms per 64 designs ({res['evals_per_s']:.0f} evals/s), eager {ms_eager:.3f} ms",
-          file=sys.stderr, flush=True)
+    res = {"designs": len(ws), "cells": cells, "form": "batched launches (tof_batch), one graph",
+           "launches_per_batch": launches, "ms_per_batch": ms, "evals_per_s": len(ws) * 1000.0 / ms,
+           "ms_per_batch_eager": ms_eager, "bytes_per_batch": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
+           "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "lengths": lengths,
+           "tile_knobs": {k: {str(L): v for L, v in d.items()} for k, d in table.items()},
+           "ms_eager_before_tuning": untuned_ms, "tune_s": round(t1 - t0, 1), "tune_trials": len(trials)}
+    print(f"[bench] c5 batched: {ms:.3f} ms per 64 designs ({res['evals_per_s']:.0f} evals/s, {launches} launches), "
+          f"eager {ms_eager:.3f} ms", file=sys.stderr, flush=True)
+    if not args.no_streams_batch:
+        t0 = time.perf_counter()
+        sched = [autotune.tune_schedule(w, "f32", evals=2)[0] for w in ws]
+        t1 = time.perf_counter()
+        b = DesignBatch(ws, "f32", [L for L, _ in sched], streams=args.batch_streams, passes=[p for _, p in sched],
+                        mode="streams")
+        sbytes = b.algorithmic_bytes()
+        sms, sms_eager = time_batch(torch, b, args.batch_replays)
+        b.close()
+        res["streams_form"] = {"form": f"each design's own launches over {args.batch_streams} streams, one graph",
+                               "launches_per_batch": 5 * len(ws), "ms_per_batch": sms,
+                               "evals_per_s": len(ws) * 1000.0 / sms, "ms_per_batch_eager": sms_eager,
+                               "bytes_per_batch": sbytes, "GBps": sbytes / (sms * 1e-3) / 1e9,
+                               "autotune_s": round(t1 - t0, 1), "lengths": [list(L) for L, _ in sched],
+                               "passes": [p for _, p in sched]}
+        print(f"[bench] c5 streams: {sms:.3f} ms per 64 designs", file=sys.stderr, flush=True)
     return res
 
 
@@ -242,7 +252,8 @@ def main():
     ap.add_argument("--no-paths", action="store_true", help="skip timing the unfused pass choices")
     ap.add_argument("--batch-replays", type=int, default=20)
     ap.add_argument("--batch-streams", type=int, default=4)
-    ap.add_argument("--no-autotune", action="store_true", help="batch with the default padded lengths")
+    ap.add_argument("--no-streams-batch", action="store_true",
+                    help="skip the comparison batch of per-design launches over streams")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB three times (a known-size kernel for "
                          "calibrating memory counters)")

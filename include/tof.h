@@ -277,8 +277,8 @@ tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[]
 const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_items);
 
 /*
- * Pass choices, each 0 or 1 (default 1); the result is the same convolution
- * either way, up to rounding order.
+ * Pass choices (options 1-3), each 0 or 1 (default 1); the result is the
+ * same convolution either way, up to rounding order.
  *   TOF_OPT_ZSUM     when the source or the target spans at most 4 z rows,
  *                    the z pass is a direct sum against the tensor
  *                    transformed along x and y, instead of FFTs along z.
@@ -298,6 +298,23 @@ const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_i
 #define TOF_OPT_ZSUM 1
 #define TOF_OPT_FUSE_YZ 2
 #define TOF_OPT_FUSE_OBJECTIVE 3
+/*
+ * Tile choices (options 4-6), the same result bit for bit, only the work
+ * split changes (for a schedule tuner):
+ *   TOF_OPT_X_TILE  tile of the x passes with power-of-two Lx: 0 (default)
+ *                   picks one row pair a block when the full tiles would
+ *                   give fewer than 512 blocks; 1 always the full tile (the
+ *                   length's compiled row pairs per block); 2 always one
+ *                   row pair a block.
+ *   TOF_OPT_GATHER_GROUPS, TOF_OPT_SCATTER_GROUPS  row groups of the fused
+ *                   y / z-sum kernels (blocks = groups x (Lx/2+1)), 1 to
+ *                   64, or 0 for the default (6 and 8, at most the rows).
+ *                   The gather's groups are added in group order, so its
+ *                   group count changes the rounding of the sum.
+ */
+#define TOF_OPT_X_TILE 4
+#define TOF_OPT_GATHER_GROUPS 5
+#define TOF_OPT_SCATTER_GROUPS 6
 tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value);
 
 /* Padded lengths chosen for the context: out[0..2] = Lx, Ly, Lz. */
@@ -318,6 +335,39 @@ size_t tof_ctx_bytes(const tof_ctx *ctx);
 
 /* Last error message of the context (or of this thread when ctx is NULL). */
 const char *tof_last_error(const tof_ctx *ctx);
+
+/*
+ * The batched form: one gradient evaluation (tof_objective_and_grad) of many
+ * independent designs, each with its own context, with one launch per pass
+ * and kernel instantiation for all of them instead of five launches per
+ * design.  tof_batch_create records every design's launches (their
+ * arguments: the context, rho[i], J[i], grad[i], as for
+ * tof_objective_and_grad) and groups them per pass; designs whose padded
+ * lengths and pass choices select the same kernels share a launch, over a
+ * device table of their arguments.  Setup-class call (allocates the table).
+ * The contexts and buffers are borrowed: they must stay valid, and their
+ * design, objective and options unchanged, while the batch is used.
+ * tof_batch_run enqueues one evaluation of every design on `stream` (no
+ * allocation, no synchronization: capturable into a graph): the launches of
+ * a pass run side by side on up to four streams the batch owns (default
+ * priority), forked from and joined back to `stream` with events; results
+ * are those of tof_objective_and_grad on each context (the same kernels).
+ * Runs of one batch must not overlap.
+ * Requires the fused passes (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ and
+ * TOF_OPT_FUSE_OBJECTIVE on, power-of-two Lx and Ly from 32 to 512, an
+ * objective on one or a few z layers) and no validation or timing.
+ * Errors: TOF_ERR_INVALID, TOF_ERR_STATE, TOF_ERR_UNSUPPORTED (a design
+ * launches a kernel with no batched form), TOF_ERR_OOM, TOF_ERR_HIP; the
+ * message is the thread's (tof_last_error(NULL)).
+ */
+typedef struct tof_batch tof_batch;
+tof_status tof_batch_create(tof_ctx *const *ctxs, const void *const *rho, double *const *J, void *const *grad,
+                            int32_t n, tof_batch **out);
+tof_status tof_batch_run(tof_batch *batch, void *stream);
+/* Kernel launches one tof_batch_run makes. */
+int32_t tof_batch_launches(const tof_batch *batch);
+/* Waits for the device, then frees the batch.  NULL is a no-op. */
+void tof_batch_destroy(tof_batch *batch);
 
 /*
  * tof_dd_newell_host -- the double-double Newell evaluation the GPU setup

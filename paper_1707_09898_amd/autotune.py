@@ -1,4 +1,4 @@
-"""Schedule autotuner: padded lengths and pass structure.
+"""Schedule autotuner: padded lengths, pass structure and tile knobs.
 
 Any padded length L >= 2n - 1 gives the same (exact) convolution, so the
 length per axis is a free schedule choice: the default is the smallest even
@@ -9,7 +9,10 @@ pass structure is free too (the same convolution up to rounding order):
 the fused y / z-sum kernels, the direct z sum in a pass of its own, or FFTs
 along z.  tune() times gradient evaluations per candidate length triple,
 tune_schedule() per (triple, pass structure) pair, on the GPU, and keeps the
-fastest; results are cached per (grid, cell, objective) key.
+fastest; results are cached per (grid, cell, objective) key.  tune_batch()
+picks the tile knobs of the batched form per padded length (x-pass tile per
+Lx, row groups of the fused gather and scatter per Ly) by timing whole
+batched evaluations.
 """
 from __future__ import annotations
 
@@ -144,3 +147,62 @@ def tune_schedule(w, dtype: str = "f32", evals: int = 3, candidates=None, passes
     _SCHED[key] = best
     _CACHE[key] = best[0]
     return best, times
+
+
+# tile knobs of the batched form, the candidates tried per padded length
+BATCH_KNOBS = {
+    "x_tile": (lambda L: [1, 2]),                       # full tile, one row pair a block
+    "gather_groups": (lambda L: [1, 2, 3, 4, 6, 8]),
+    "scatter_groups": (lambda L: [1, 2, 4, 8]),
+}
+
+
+def _knob_option(name):
+    from . import tof
+    return {"x_tile": tof.OPT_X_TILE, "gather_groups": tof.OPT_GATHER_GROUPS,
+            "scatter_groups": tof.OPT_SCATTER_GROUPS}[name]
+
+
+def _knob_axis(name):
+    return 0 if name == "x_tile" else 1   # the x tile follows Lx; the fused y / z sums follow Ly
+
+
+def apply_batch_knobs(b, table):
+    """Set table[name][L] on every engine of batch b whose padded length
+    along the knob's axis is L, then re-record the batch."""
+    for e in b.engines:
+        L = e.padded_lengths()
+        for name, per_len in table.items():
+            v = per_len.get(L[_knob_axis(name)])
+            if v is not None:
+                e.set_option(_knob_option(name), int(v))
+    b.rebatch()
+
+
+def tune_batch(b, evals: int = 5, rounds: int = 1):
+    """Coordinate search over the tile knobs of a batched DesignBatch: for
+    every knob and every padded length present along its axis, each
+    candidate value is timed on the whole batch (eager launches, median of 3
+    loops) and the fastest kept.  Returns (table {knob: {L: value}}, best ms,
+    {(knob, L, value): ms})."""
+    lens = {name: sorted({e.padded_lengths()[_knob_axis(name)] for e in b.engines}) for name in BATCH_KNOBS}
+    table = {name: {L: BATCH_KNOBS[name](L)[0] for L in lens[name]} for name in BATCH_KNOBS}
+    apply_batch_knobs(b, table)
+    best = b.time_eager(evals)
+    trials = {}
+    for _ in range(rounds):
+        for name in BATCH_KNOBS:
+            for L in lens[name]:
+                keep = table[name][L]
+                for v in BATCH_KNOBS[name](L):
+                    if v == keep:
+                        continue
+                    table[name][L] = v
+                    apply_batch_knobs(b, table)
+                    ms = b.time_eager(evals)
+                    trials[(name, L, v)] = ms
+                    if ms < best:
+                        best, keep = ms, v
+                table[name][L] = keep
+                apply_batch_knobs(b, table)
+    return table, best, trials

@@ -1,17 +1,43 @@
-"""Batching form: many independent designs, each with its own context, run
-as one HIP graph.
+"""Batching form: many independent designs, each with its own context,
+evaluated together.
 
-Every design keeps its density, gradient and J resident on the device.  The
-gradient evaluations are recorded once into a graph (torch.cuda.CUDAGraph
-over the library's own launches): the designs are spread over several
-streams forked from the capture stream (balanced by padded volume), so
-independent designs overlap on the GPU, and one replay evaluates the whole
-batch.  Each context owns its
-workspaces, so concurrent designs share nothing.
+Every design keeps its density, gradient and J resident on the device.  Two
+modes:
+
+* ``batched`` (default): the library's batched form (tof_batch): one launch
+  per pass and kernel instantiation for all designs, each launch over a
+  device table of the designs' arguments, so the whole batch is a handful
+  of launches (designs with the same padded lengths share them).  It needs
+  the fused passes, hence power-of-two padded lengths along x and y
+  (``batch_lengths``).
+* ``streams``: every design's own five launches, spread over several streams
+  forked from the capture stream (balanced by padded volume), so
+  independent designs overlap on the GPU.
+
+Either way one evaluation of the batch can be recorded into a graph
+(torch.cuda.CUDAGraph over the library's own launches) and replayed.  Each
+context owns its workspaces, so concurrent designs share nothing.
 """
 from __future__ import annotations
 
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
+
+
+def pow2_at_least(v: int, lo: int = 32) -> int:
+    p = lo
+    while p < v:
+        p *= 2
+    return p
+
+
+def batch_lengths(w) -> Tuple[int, int, int]:
+    """Padded lengths for the batched form: the smallest powers of two
+    >= 2n - 1 along x and y (at least 32; the fused kernels' register
+    transforms), the library's rule along z (the fused passes sum along z
+    directly and never transform along it)."""
+    from .autotune import default_length
+    nx, ny, nz = w.n
+    return (pow2_at_least(2 * nx - 1), pow2_at_least(2 * ny - 1), default_length(nz))
 
 
 def balance(cost: Sequence[float], nstreams: int) -> List[List[int]]:
@@ -29,12 +55,20 @@ def balance(cost: Sequence[float], nstreams: int) -> List[List[int]]:
 
 class DesignBatch:
     def __init__(self, workloads: Sequence, dtype: str = "f32", lengths: Optional[Sequence] = None,
-                 streams: int = 4, passes: Optional[Sequence[str]] = None):
+                 streams: int = 4, passes: Optional[Sequence[str]] = None, mode: str = "batched"):
         import torch
         from . import autotune, tof
+        if mode not in ("batched", "streams"):
+            raise ValueError("mode is 'batched' or 'streams'")
         self.torch = torch
+        self.mode = mode
         self.workloads = list(workloads)
         self.dtype = dtype
+        if mode == "batched":
+            if lengths is None:
+                lengths = [batch_lengths(w) for w in self.workloads]
+            if passes is not None and any(p != "fused" for p in passes):
+                raise ValueError("the batched mode runs the fused passes only")
         self.engines = []
         self.rho, self.grad, self.J = [], [], []
         for i, w in enumerate(self.workloads):
@@ -50,6 +84,37 @@ class DesignBatch:
         self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
         self.assignment = self._balance(len(self.streams))
         self.graph = None
+        self.batch = tof.Batch(self.engines, self.rho, self.J, self.grad) if mode == "batched" else None
+
+    def rebatch(self):
+        """Record the batched launches again (after a change of the engines'
+        options); any captured graph is dropped."""
+        from . import tof
+        self.graph = None
+        if self.batch is not None:
+            self.batch.close()
+        self.batch = tof.Batch(self.engines, self.rho, self.J, self.grad)
+
+    def time_eager(self, evals: int = 5, repeats: int = 3) -> float:
+        """ms per batch evaluation launched eagerly (median of `repeats` loops)."""
+        torch = self.torch
+        self.run_eager()
+        out = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(evals):
+                self.run_eager()
+            t1.record()
+            torch.cuda.synchronize()
+            out.append(t0.elapsed_time(t1) / evals)
+        return sorted(out)[len(out) // 2]
+
+    def launches(self) -> int:
+        """Kernel launches of one evaluation of the batch."""
+        return self.batch.launches() if self.batch is not None else 5 * len(self.engines)
 
     def _balance(self, nstreams: int) -> List[List[int]]:
         """Designs per stream, balanced by padded volume (see balance)."""
@@ -63,7 +128,11 @@ class DesignBatch:
         return len(self.engines)
 
     def _enqueue(self, root):
-        """Fork the side streams from `root`, enqueue every design, join back."""
+        """Enqueue one evaluation of every design on `root` (batched), or fork
+        the side streams from `root`, enqueue every design, join back."""
+        if self.batch is not None:
+            self.batch.run(stream=root)
+            return
         for s in self.streams:
             s.wait_stream(root)
         for s, designs in zip(self.streams, self.assignment):
@@ -112,6 +181,9 @@ class DesignBatch:
 
     def close(self):
         self.graph = None
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
         for e in self.engines:
             e.close()
         self.engines = []

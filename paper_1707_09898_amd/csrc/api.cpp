@@ -17,6 +17,8 @@
 
 thread_local const char *g_last_kernel = "";
 thread_local long long g_last_items = 0;
+thread_local std::vector<BatchLaunch> *g_batch_record = nullptr;
+thread_local const char *g_batch_unbatchable = nullptr;
 
 namespace {
 
@@ -92,8 +94,48 @@ struct tof_ctx {
     bool opt_zsum = true;    // direct z sum against Kt for few source / target rows
     bool opt_fuse = true;    // that sum fused with the y transforms
     bool opt_fuse_obj = true;   // the objective fused with the adjoint's x pass
+    int opt_xtile = kXTileAuto;    // tile of the register x passes
+    int opt_gather_groups = 0;     // row groups of the fused gather (0: the default rule)
+    int opt_scatter_groups = 0;    // row groups of the fused scatter (0: the default rule)
     std::string err;
 };
+
+// The batched form: the launches of one gradient evaluation of every design,
+// grouped per pass into one launch per kernel instantiation over a device
+// table of the designs' arguments.
+struct tof_batch {
+    struct Group {
+        const void *kernel;   // batched kernel: (const Args *table, const int *starts, int n)
+        dim3 block;
+        int n = 0;             // designs in the group
+        long long blocks = 0;  // total blocks of the launch
+        void *tab = nullptr;   // device: n argument structs
+        int *starts = nullptr; // device: n + 1 first-block indices
+    };
+    std::vector<std::vector<Group>> passes;
+    void *buf = nullptr;   // one device allocation holding every table
+    // the groups of a pass run side by side on these streams (default
+    // priority), joined to the caller's stream between passes
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;   // [0]: the caller's stream; [1 + i]: stream i
+    std::string err;
+};
+
+constexpr int kBatchStreams = 4;
+// Side streams are off: forking a pass's groups onto them and joining back
+// with events measured slower than running the groups one after another
+// (each join left 30-40 us with no kernel running).
+constexpr int kBatchSideStreams = 0;
+
+void batch_release(tof_batch *b)
+{
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    if (b->buf) (void)hipFree(b->buf);
+    b->events.clear();
+    b->streams.clear();
+    b->buf = nullptr;
+}
 
 namespace {
 
@@ -373,7 +415,7 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                                   : prod.c_out * nTrow * T.nx() * w;
     if (!a_ready) {   // else the caller's kernel has written the x pass output into A
         HIP_TRY(ctx, timed(ctx, st, slot0 + 0, src_bytes + a_elems * cw, [&] {
-            return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx);
+            return launch_x_forward<R>(st, mode, dsg, src, S, prod.c_in, plx, A, hx, ctx->opt_xtile);
         }));
     }
     const bool zsum_counts = (prod.c_in == 1 || prod.c_in == 3) && (prod.c_out == 1 || prod.c_out == 3);
@@ -387,7 +429,8 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         const bool gather = T.nz() <= kZsumMaxRows;
         const int rows = gather ? S.nz() : T.nz();
         // the gather's partial rows must fit in B
-        int G = std::max(1, std::min(rows, gather ? TOF_YZ_GATHER_GROUPS : TOF_YZ_SCATTER_GROUPS));
+        const int Gopt = gather ? ctx->opt_gather_groups : ctx->opt_scatter_groups;
+        int G = std::max(1, std::min(rows, Gopt > 0 ? Gopt : (gather ? TOF_YZ_GATHER_GROUPS : TOF_YZ_SCATTER_GROUPS)));
         // the gather's partial copies of the inverse x input (y space), added by that pass
         const long long part_rows = (long long)prod.c_out * hx * T.nz() * T.ny();
         if (gather) G = (int)std::max(1LL, std::min<long long>(G, (long long)(ctx->B.bytes / sizeof(cplx<R>)) / part_rows));
@@ -409,7 +452,7 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                 }
                 HIP_TRY(ctx, timed(ctx, st, slot0 + 4, part_bytes + x_out, [&] {
                     return launch_x_inverse<R>(st, B, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest,
-                                               G, part_rows);
+                                               G, part_rows, ctx->opt_xtile);
                 }));
                 return TOF_OK;
             }
@@ -423,7 +466,8 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
                 return TOF_OK;
             }
             HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
-                return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest);
+                return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest, 1,
+                                           0, ctx->opt_xtile);
             }));
             return TOF_OK;
         }
@@ -453,7 +497,8 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         return TOF_OK;
     }
     HIP_TRY(ctx, timed(ctx, st, slot0 + 4, c_elems * cw + x_out, [&] {
-        return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest);
+        return launch_x_inverse<R>(st, C, hx, prod.c_out, T, plx, grad_epi, out, dsg, m0u, grad, zero_rest, 1, 0,
+                                   ctx->opt_xtile);
     }));
     return TOF_OK;
 }
@@ -1095,11 +1140,21 @@ const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_i
 tof_status tof_set_option(tof_ctx *ctx, int32_t option, int32_t value)
 {
     if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
-    if (value != 0 && value != 1) return fail(ctx, TOF_ERR_INVALID, "option values are 0 or 1");
+    const bool flag = option >= TOF_OPT_ZSUM && option <= TOF_OPT_FUSE_OBJECTIVE;
+    if (flag && value != 0 && value != 1) return fail(ctx, TOF_ERR_INVALID, "option values are 0 or 1");
     switch (option) {
     case TOF_OPT_ZSUM: ctx->opt_zsum = value != 0; return TOF_OK;
     case TOF_OPT_FUSE_YZ: ctx->opt_fuse = value != 0; return TOF_OK;
     case TOF_OPT_FUSE_OBJECTIVE: ctx->opt_fuse_obj = value != 0; return TOF_OK;
+    case TOF_OPT_X_TILE:
+        if (value < kXTileAuto || value > kXTilePair) return fail(ctx, TOF_ERR_INVALID, "x tile is 0, 1 or 2");
+        ctx->opt_xtile = value;
+        return TOF_OK;
+    case TOF_OPT_GATHER_GROUPS:
+    case TOF_OPT_SCATTER_GROUPS:
+        if (value < 0 || value > 64) return fail(ctx, TOF_ERR_INVALID, "row groups are 0 (default) to 64");
+        (option == TOF_OPT_GATHER_GROUPS ? ctx->opt_gather_groups : ctx->opt_scatter_groups) = value;
+        return TOF_OK;
     default: return fail(ctx, TOF_ERR_INVALID, "unknown option");
     }
 }
@@ -1138,6 +1193,179 @@ const char *tof_last_error(const tof_ctx *ctx)
 {
     if (ctx) return ctx->err.c_str();
     return g_thread_error.c_str();
+}
+
+tof_status tof_batch_create(tof_ctx *const *ctxs, const void *const *rho, double *const *J, void *const *grad,
+                            int32_t n, tof_batch **out)
+{
+    if (!out) return fail(nullptr, TOF_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (!ctxs || !rho || !J || !grad || n < 1) return fail(nullptr, TOF_ERR_INVALID, "null arrays or n < 1");
+    // record every design's launches (nothing runs)
+    std::vector<std::vector<BatchLaunch>> recs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        tof_ctx *ctx = ctxs[i];
+        tof_status s = check_ready(ctx, true);
+        if (s != TOF_OK) return fail(nullptr, s, "design " + std::to_string(i) + ": " + g_thread_error);
+        if (!rho[i] || !J[i] || !grad[i]) return fail(nullptr, TOF_ERR_INVALID, "null buffer of design " + std::to_string(i));
+        if (ctx->validate || ctx->prof_on)
+            return fail(nullptr, TOF_ERR_INVALID, "design " + std::to_string(i) + ": no validation or timing in a batch");
+        g_batch_record = &recs[i];
+        g_batch_unbatchable = nullptr;
+        s = ctx->f64 ? run_objective_and_grad<double>(ctx, nullptr, rho[i], J[i], grad[i])
+                     : run_objective_and_grad<float>(ctx, nullptr, rho[i], J[i], grad[i]);
+        const char *bad = g_batch_unbatchable;
+        g_batch_record = nullptr;
+        g_batch_unbatchable = nullptr;
+        if (s != TOF_OK) return fail(nullptr, s, "design " + std::to_string(i) + ": " + ctx->err);
+        if (bad)
+            return fail(nullptr, TOF_ERR_UNSUPPORTED, "design " + std::to_string(i) + " launches " + bad +
+                                                         ", which has no batched form (the batch needs the fused passes)");
+        if (recs[i].size() != recs[0].size())
+            return fail(nullptr, TOF_ERR_UNSUPPORTED, "design " + std::to_string(i) + " has a different number of passes");
+    }
+    tof_batch *b = new (std::nothrow) tof_batch();
+    if (!b) return fail(nullptr, TOF_ERR_OOM, "host allocation failed");
+    // group per pass by (kernel, block); lay the tables out in one host image
+    std::vector<unsigned char> image;
+    struct Pending { size_t tab_off, starts_off; };
+    std::vector<std::vector<Pending>> pend;
+    const size_t npass = recs[0].size();
+    b->passes.resize(npass);
+    pend.resize(npass);
+    auto align = [&](size_t a) { image.resize((image.size() + a - 1) / a * a); };
+    for (size_t k = 0; k < npass; ++k) {
+        std::vector<int> done((size_t)n, 0);
+        for (int i = 0; i < n; ++i) {
+            if (done[i]) continue;
+            const BatchLaunch &r0 = recs[i][k];
+            tof_batch::Group g;
+            g.kernel = r0.kernel;
+            g.block = r0.block;
+            std::vector<int> members;
+            for (int j = i; j < n; ++j) {
+                const BatchLaunch &r = recs[j][k];
+                if (!done[j] && r.kernel == r0.kernel && r.block.x == r0.block.x && r.block.y == r0.block.y &&
+                    r.block.z == r0.block.z && r.args.size() == r0.args.size()) {
+                    members.push_back(j);
+                    done[j] = 1;
+                }
+            }
+            g.n = (int)members.size();
+            align(256);
+            const size_t tab_off = image.size();
+            for (int j : members) image.insert(image.end(), recs[j][k].args.begin(), recs[j][k].args.end());
+            align(256);
+            const size_t starts_off = image.size();
+            std::vector<int> starts;
+            long long tot = 0;
+            for (int j : members) {
+                starts.push_back((int)tot);
+                const dim3 &gr = recs[j][k].grid;
+                tot += (long long)gr.x * gr.y * gr.z;
+            }
+            starts.push_back((int)tot);
+            if (tot > (1LL << 30)) {
+                delete b;
+                return fail(nullptr, TOF_ERR_UNSUPPORTED, "batch too large for one launch");
+            }
+            g.blocks = tot;
+            const unsigned char *sp = reinterpret_cast<const unsigned char *>(starts.data());
+            image.insert(image.end(), sp, sp + sizeof(int) * starts.size());
+            b->passes[k].push_back(g);
+            pend[k].push_back(Pending{tab_off, starts_off});
+        }
+    }
+    hipError_t e = hipMalloc(&b->buf, image.size());
+    if (e == hipSuccess) e = hipMemcpy(b->buf, image.data(), image.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (b->buf) (void)hipFree(b->buf);
+        delete b;
+        return hip_fail(nullptr, e, "tof_batch_create");
+    }
+    for (size_t k = 0; k < npass; ++k)
+        for (size_t q = 0; q < b->passes[k].size(); ++q) {
+            b->passes[k][q].tab = (unsigned char *)b->buf + pend[k][q].tab_off;
+            b->passes[k][q].starts = (int *)((unsigned char *)b->buf + pend[k][q].starts_off);
+        }
+    size_t widest = 0;
+    for (const auto &pass : b->passes) widest = std::max(widest, pass.size());
+    const int ns = (int)std::min<size_t>(kBatchStreams, widest > 1 ? widest : 0) * kBatchSideStreams;
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        hipStream_t sti = nullptr;
+        e = hipStreamCreateWithFlags(&sti, hipStreamNonBlocking);
+        if (e == hipSuccess) b->streams.push_back(sti);
+    }
+    for (int i = 0; i < (ns ? ns + 1 : 0) && e == hipSuccess; ++i) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->events.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        batch_release(b);
+        delete b;
+        return hip_fail(nullptr, e, "tof_batch_create (streams)");
+    }
+    *out = b;
+    return TOF_OK;
+}
+
+tof_status tof_batch_run(tof_batch *b, void *stream)
+{
+    if (!b) return fail(nullptr, TOF_ERR_INVALID, "null batch");
+    hipStream_t st = (hipStream_t)stream;
+    auto check = [&](hipError_t e, const char *what) {
+        if (e == hipSuccess) return TOF_OK;
+        b->err = std::string(what) + ": " + hipGetErrorString(e);
+        return fail(nullptr, TOF_ERR_HIP, b->err);
+    };
+    tof_status s;
+    for (const auto &pass : b->passes) {
+        // one group: on the caller's stream; several: side by side on the
+        // batch's streams, which start after everything before on the
+        // caller's stream and which the caller's stream then waits for
+        const bool fork = pass.size() > 1 && !b->streams.empty();
+        const int ns = fork ? (int)std::min(pass.size(), b->streams.size()) : 0;
+        if (fork) {
+            if ((s = check(hipEventRecord(b->events[0], st), "hipEventRecord")) != TOF_OK) return s;
+            for (int i = 0; i < ns; ++i)
+                if ((s = check(hipStreamWaitEvent(b->streams[i], b->events[0], 0), "hipStreamWaitEvent")) != TOF_OK)
+                    return s;
+        }
+        for (size_t q = 0; q < pass.size(); ++q) {
+            const tof_batch::Group &g = pass[q];
+            const void *tab = g.tab;
+            const int *starts = g.starts;
+            int n = g.n;
+            void *args[] = {(void *)&tab, (void *)&starts, (void *)&n};
+            hipStream_t sq = fork ? b->streams[q % ns] : st;
+            if ((s = check(hipLaunchKernel(g.kernel, dim3((unsigned)g.blocks), g.block, args, 0, sq),
+                           "hipLaunchKernel")) != TOF_OK)
+                return s;
+        }
+        if (fork)
+            for (int i = 0; i < ns; ++i) {
+                if ((s = check(hipEventRecord(b->events[1 + i], b->streams[i]), "hipEventRecord")) != TOF_OK) return s;
+                if ((s = check(hipStreamWaitEvent(st, b->events[1 + i], 0), "hipStreamWaitEvent")) != TOF_OK) return s;
+            }
+    }
+    return TOF_OK;
+}
+
+int32_t tof_batch_launches(const tof_batch *b)
+{
+    if (!b) return 0;
+    int32_t c = 0;
+    for (const auto &pass : b->passes) c += (int32_t)pass.size();
+    return c;
+}
+
+void tof_batch_destroy(tof_batch *b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    batch_release(b);
+    delete b;
 }
 
 double tof_dd_newell_host(int32_t c, int32_t kx, int32_t ky, int32_t kz, double dx, double dy, double dz)

@@ -121,4 +121,29 @@ __device__ __forceinline__ void finalize_j(const JFinal &jf)
     if (lane == 0) *jf.J = jf.div ? total / jf.c : jf.c * total;
 }
 
+// In a batched launch (a one-dimensional grid over the blocks of n designs,
+// design d owning blocks starts[d] .. starts[d+1] - 1): the calling block's
+// design d (a uniform binary search), its arguments and its place in that
+// design's own grid.
+template <typename A>
+__device__ __forceinline__ A batch_args(const A *__restrict__ tab, const int *__restrict__ starts, int n, BlockPos &bp)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (starts[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const A a = tab[lo];
+    const int local = b - starts[lo];
+    bp.gx_ = a.bg.gx;
+    bp.gy_ = a.bg.gy;
+    bp.gz_ = a.bg.gz;
+    bp.x_ = local % bp.gx_;
+    bp.y_ = (local / bp.gx_) % bp.gy_;
+    bp.z_ = local / (bp.gx_ * bp.gy_);
+    return a;
+}
+
 }  // namespace tofdev

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+#include <vector>
+
 #include "fft.h"
 
 struct Box {
@@ -125,6 +128,62 @@ struct YzSumArgs {
     JFinal jf;               // scatter: J to form first (block (0, 0), one wave), or none
 };
 
+// Block coordinates a pass kernel's body works on: its launch's own
+// (HerePos: blockIdx and gridDim, read where used), or, in a batched launch,
+// the block's place in the grid of its design (BlockPos).
+struct BlockPos {
+    int x_, y_, z_;
+    int gx_, gy_, gz_;
+    __device__ int x() const { return x_; }
+    __device__ int y() const { return y_; }
+    __device__ int z() const { return z_; }
+    __device__ int gx() const { return gx_; }
+    __device__ int gy() const { return gy_; }
+    __device__ int gz() const { return gz_; }
+};
+struct HerePos {
+    __device__ int x() const { return blockIdx.x; }
+    __device__ int y() const { return blockIdx.y; }
+    __device__ int z() const { return blockIdx.z; }
+    __device__ int gx() const { return gridDim.x; }
+    __device__ int gy() const { return gridDim.y; }
+    __device__ int gz() const { return gridDim.z; }
+};
+
+// Grid of one design's launch; the first member of every argument struct of
+// a kernel that can run batched (the batched launch reads it per design).
+struct BatchGrid {
+    int gx, gy, gz;
+};
+
+// A launch recorded for the batched form: the batched kernel of the same
+// instantiation (parameters: const Args *table, const int *starts, int n),
+// the launch's own grid and block, and its argument struct.
+struct BatchLaunch {
+    const void *kernel;
+    dim3 grid, block;
+    std::vector<unsigned char> args;
+};
+
+// While set, the launchers of the batchable kernels append their launch here
+// instead of launching, and any other launch sets g_batch_unbatchable to its
+// kernel's text and is skipped.
+extern thread_local std::vector<BatchLaunch> *g_batch_record;
+extern thread_local const char *g_batch_unbatchable;
+
+template <typename A>
+inline void batch_record(const void *kernel, dim3 grid, dim3 block, A a)
+{
+    a.bg = BatchGrid{(int)grid.x, (int)grid.y, (int)grid.z};
+    BatchLaunch bl;
+    bl.kernel = kernel;
+    bl.grid = grid;
+    bl.block = block;
+    bl.args.resize(sizeof(A));
+    std::memcpy(bl.args.data(), &a, sizeof(A));
+    g_batch_record->push_back(std::move(bl));
+}
+
 // Text of the kernel expression last launched by this thread and its work
 // items (grid times block), for the per-launch timing record; set by TOF_LAUNCH.
 extern thread_local const char *g_last_kernel;
@@ -134,14 +193,36 @@ extern thread_local long long g_last_items;
         g_last_kernel = #K;                                                                       \
         const dim3 g_ = dim3(G), b_ = dim3(B);                                                    \
         g_last_items = (long long)g_.x * g_.y * g_.z * b_.x * b_.y * b_.z;                        \
+        if (g_batch_record) {                                                                     \
+            g_batch_unbatchable = #K;                                                             \
+            break;                                                                                \
+        }                                                                                         \
         hipLaunchKernelGGL(K, g_, b_, __VA_ARGS__);                                               \
+    } while (0)
+
+// Launch of a batchable kernel K with the kernel arguments that follow A
+// (no dynamic LDS), or, while recording, the record of argument struct A
+// with the batched kernel KB.
+#define TOF_LAUNCH_B(K, KB, G, B, st, A, ...)                                                     \
+    do {                                                                                          \
+        if (g_batch_record) {                                                                     \
+            batch_record(reinterpret_cast<const void *>(KB), dim3(G), dim3(B), A);                \
+            break;                                                                                \
+        }                                                                                         \
+        TOF_LAUNCH(K, G, B, 0, st, __VA_ARGS__);                                                  \
     } while (0)
 
 // ---- host launchers (kernels.hip); all enqueue on `st` and return hipError_t ----
 
+// Tiles of the register x passes (power-of-two lengths): the full tile of
+// the length's knobs (several row pairs a block), one row pair a block, or
+// (auto) one row pair a block when the full tiles would give fewer than 512
+// blocks.
+constexpr int kXTileAuto = 0, kXTileFull = 1, kXTilePair = 2;
+
 template <typename R>
 hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
-                            Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx);
+                            Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx, int xtile = kXTileAuto);
 
 template <typename R>
 hipError_t launch_line_fft(hipStream_t st, const cplx<R> *in, cplx<R> *out, int nlines, int inner,
@@ -181,7 +262,7 @@ template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
                             const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside, int nsum = 1,
-                            long long sum_stride = 0);
+                            long long sum_stride = 0, int xtile = kXTileAuto);
 
 // blocks the objective kernel may use (partials buffer length)
 constexpr int kObjMaxBlocks = 1024;

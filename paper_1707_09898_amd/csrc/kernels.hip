@@ -102,6 +102,49 @@ __device__ __forceinline__ R source_value(int mode, const DesignDev<R> &d, const
     return v;
 }
 
+// Arguments of the register x passes (one design).
+template <typename R>
+struct XfArgs {
+    BatchGrid bg;
+    int mode;
+    DesignDev<R> dsg;
+    View4<const R> src;
+    Box S;
+    cplx<R> *out;
+    int hx;
+    const cplx<R> *table;
+};
+
+template <typename R>
+struct XiArgs {
+    BatchGrid bg;
+    const cplx<R> *C;
+    int hx;
+    Box T;
+    int grad_epi;
+    View4<R> out;
+    DesignDev<R> dsg;
+    R m0u0, m0u1, m0u2;
+    R *grad;
+    const cplx<R> *table;
+    int zrows;
+    int nsum;
+    long long sum_stride;
+};
+
+template <typename R>
+struct ObjXfArgs {
+    BatchGrid bg;
+    ObjectiveDev<R> o;
+    cplx<R> *out;
+    int hx;
+    const cplx<R> *table;
+    const cplx<R> *spec;
+    int nsum;
+    long long sum_stride;
+    int kxf;
+};
+
 // ---------------------------------------------------------------------------
 // Pass 1: real-to-complex FFT along x of TY source rows (one z, one component).
 // Two real rows share one complex line (a + i b); the two half spectra are
@@ -669,10 +712,8 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
 // rows ty0 + 2l, ty0 + 2l + 1 back along x from their kx spectra (nsum
 // copies sum_stride apart, added in order; [cc][kx][zrel][y], or with kxf
 // [cc][zrel][y][kx]), so the field is never stored.
-template <typename R, int L, int E>
-__global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
-                                                            const cplx<R> *table, const cplx<R> *spec, int nsum,
-                                                            long long sum_stride, int kxf)
+template <typename R, int L, int E, typename BP>
+__device__ __forceinline__ void objective_xf_body(const ObjectiveDev<R> &o, cplx<R> *out, int hx, const cplx<R> *table, const cplx<R> *spec, int nsum, long long sum_stride, int kxf, const BP bp)
 {
     constexpr int P = L / E;
     constexpr int NLN = 3;
@@ -688,10 +729,10 @@ __global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o,
     const int tid = threadIdx.x;
     const int l = line_of_thread<P>();
     const int p = tid % P;
-    const int cc = blockIdx.z;
-    const int zrel = blockIdx.y;
+    const int cc = bp.z();
+    const int zrel = bp.y();
     const int z = ob.z0 + zrel;
-    const int ybase = ob.y0 + 2 * blockIdx.x;
+    const int ybase = ob.y0 + 2 * bp.x();
     const bool two = ybase + 1 < ob.y1;
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
@@ -830,7 +871,24 @@ __global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o,
                                   : cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
     }
     // the block's J terms; J itself is formed from these by a later kernel
-    if (tid == 0) o.partials[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = jsum;
+    if (tid == 0) o.partials[(bp.z() * bp.gy() + bp.y()) * bp.gx() + bp.x()] = jsum;
+}
+
+template <typename R, int L, int E>
+__global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
+                                                            const cplx<R> *table, const cplx<R> *spec, int nsum,
+                                                            long long sum_stride, int kxf)
+{
+    objective_xf_body<R, L, E>(o, out, hx, table, spec, nsum, sum_stride, kxf, HerePos{});
+}
+
+template <typename R, int L, int E>
+__global__ __launch_bounds__(3 * (L / E)) void k_objective_xf_batch(const ObjXfArgs<R> *__restrict__ tab,
+                                                                   const int *__restrict__ starts, int n)
+{
+    BlockPos bp;
+    const ObjXfArgs<R> a = batch_args(tab, starts, n, bp);
+    objective_xf_body<R, L, E>(a.o, a.out, a.hx, a.table, a.spec, a.nsum, a.sum_stride, a.kxf, bp);
 }
 
 // One wave: J from the objective's block sums.
@@ -1366,9 +1424,8 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 // each thread transforms LPT of them in turn.  HALF (design sources only):
 // the design rows fill exactly the lower half of the line (x in [0, L/2)),
 // so the upper half is neither loaded nor transformed in the first stage.
-template <typename R, int L, int E, int NLC, int LPT, bool HALF>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
-                                                                Box S, cplx<R> *out, int hx, const cplx<R> *table)
+template <typename R, int L, int E, int NLC, int LPT, bool HALF, typename BP>
+__device__ __forceinline__ void xf_reg_body(int mode, const DesignDev<R> &dsg, const View4<const R> &src, const Box &S, cplx<R> *out, int hx, const cplx<R> *table, const BP bp)
 {
     constexpr int ME = HALF ? E / 2 : E;   // slots that can hold data
     constexpr int P = L / E;
@@ -1378,10 +1435,10 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
     __shared__ cplx<R> lds[NLC * PITCH];
     const int l0 = line_of_thread<P>();
     const int p = threadIdx.x % P;
-    const int c = blockIdx.z;
-    const int zrel = blockIdx.y;
+    const int c = bp.z();
+    const int zrel = bp.y();
     const int z = S.z0 + zrel;
-    const int ybase = S.y0 + blockIdx.x * TY;
+    const int ybase = S.y0 + bp.x() * TY;
     const int nrow = min(TY, S.y1 - ybase);
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
@@ -1492,20 +1549,33 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
     }
 }
 
+template <typename R, int L, int E, int NLC, int LPT, bool HALF>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
+                                                                Box S, cplx<R> *out, int hx, const cplx<R> *table)
+{
+    xf_reg_body<R, L, E, NLC, LPT, HALF>(mode, dsg, src, S, out, hx, table, HerePos{});
+}
+
+template <typename R, int L, int E, int NLC, int LPT, bool HALF>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg_batch(
+    const XfArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+{
+    BlockPos bp;
+    const XfArgs<R> a = batch_args(tab, starts, n, bp);
+    xf_reg_body<R, L, E, NLC, LPT, HALF>(a.mode, a.dsg, a.src, a.S, a.out, a.hx, a.table, bp);
+}
+
 // -- pass 5: complex-to-real inverse FFT along x + epilogue -----------------
 // Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
 // each thread transforms LPT lines in turn.  HALF: every column the pass
 // stores lies in the lower half of the line (x < L/2).
-template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF>
-__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? (sizeof(R) == 8 ? TOF_XI_WAVES_F64 : TOF_XI_WAVES) : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
-                                                                View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
-                                                                R m0u2, R *grad, const cplx<R> *table, int zrows,
-                                                                int nsum, long long sum_stride)
+template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF, typename BP>
+__device__ __forceinline__ void xi_reg_body(const cplx<R> *C, int hx, const Box &T, int grad_epi, const View4<R> &out, const DesignDev<R> &dsg, R m0u0, R m0u1, R m0u2, R *grad, const cplx<R> *table, int zrows, int nsum, long long sum_stride, const BP bp)
 {
-    if ((int)blockIdx.y >= T.nz()) {
+    if ((int)bp.y() >= T.nz()) {
         // blocks past the target rows zero the gradient rows outside the design
         // box (T is the design box then); the whole block leaves here
-        const int q0 = ((blockIdx.y - T.nz()) * gridDim.x + blockIdx.x) * kZeroRowsPerBlock;
+        const int q0 = ((bp.y() - T.nz()) * bp.gx() + bp.x()) * kZeroRowsPerBlock;
         for (int j = 0; j < kZeroRowsPerBlock && q0 + j < zrows; ++j) {
             int y, z;
             outside_row(q0 + j, dsg.ny, dsg.design, y, z);
@@ -1524,9 +1594,9 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
     __shared__ cplx<R> lds[NLDS];
     const int l0 = line_of_thread<P>();
     const int p = threadIdx.x % P;
-    const int zrel = blockIdx.y;
+    const int zrel = bp.y();
     const int z = T.z0 + zrel;
-    const int ybase = T.y0 + blockIdx.x * TY;
+    const int ybase = T.y0 + bp.x() * TY;
     const int nrow = min(TY, T.y1 - ybase);
     const int nyt = T.ny(), nzt = T.nz();
     cplx<R> tw[NT > 0 ? NT : 1];
@@ -1697,6 +1767,24 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
     }
 }
 
+template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? (sizeof(R) == 8 ? TOF_XI_WAVES_F64 : TOF_XI_WAVES) : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
+                                                                View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
+                                                                R m0u2, R *grad, const cplx<R> *table, int zrows,
+                                                                int nsum, long long sum_stride)
+{
+    xi_reg_body<R, L, E, NLC, LPT, CO, PS, HALF>(C, hx, T, grad_epi, out, dsg, m0u0, m0u1, m0u2, grad, table, zrows, nsum, sum_stride, HerePos{});
+}
+
+template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF>
+__global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? (sizeof(R) == 8 ? TOF_XI_WAVES_F64 : TOF_XI_WAVES) : 1))) void k_xi_reg_batch(const XiArgs<R> *__restrict__ tab, const int *__restrict__ starts,
+                                                         int n)
+{
+    BlockPos bp;
+    const XiArgs<R> a = batch_args(tab, starts, n, bp);
+    xi_reg_body<R, L, E, NLC, LPT, CO, PS, HALF>(a.C, a.hx, a.T, a.grad_epi, a.out, a.dsg, a.m0u0, a.m0u1, a.m0u2, a.grad, a.table, a.zrows, a.nsum, a.sum_stride, bp);
+}
+
 // ---- launch configuration helpers ----
 
 constexpr size_t kLdsBudget = 64 * 1024;
@@ -1758,49 +1846,52 @@ hipError_t allow_lds(K kernel, size_t bytes)
 
 template <typename R, int L, int NLC, int LPT, bool HALF>
 hipError_t launch_xf_reg_h(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
-                           const FftPlanDev &plan, cplx<R> *out, int hx)
+                           const FftPlanDev &plan, cplx<R> *out, int hx, int xtile)
 {
     constexpr int E = 8;
-    if ((long long)((S.ny() + 2 * NLC - 1) / (2 * NLC)) * S.nz() * c_in < 512) {
+    const bool few = (long long)((S.ny() + 2 * NLC - 1) / (2 * NLC)) * S.nz() * c_in < 512;
+    if (xtile == kXTilePair || (xtile == kXTileAuto && few)) {
         // few rows: one row pair per block
         dim3 grid((S.ny() + 1) / 2, S.nz(), c_in);
-        TOF_LAUNCH((k_xf_reg<R, L, E, 1, 1, HALF>), grid, dim3(L / E), 0, st, mode, dsg, src, S, out, hx,
-                           (const cplx<R> *)plan.tw);
+        const XfArgs<R> a{{}, mode, dsg, src, S, out, hx, (const cplx<R> *)plan.tw};
+        TOF_LAUNCH_B((k_xf_reg<R, L, E, 1, 1, HALF>), (k_xf_reg_batch<R, L, E, 1, 1, HALF>), grid, dim3(L / E), st, a,
+                     mode, dsg, src, S, out, hx, (const cplx<R> *)plan.tw);
         return hipGetLastError();
     }
     dim3 grid((S.ny() + 2 * NLC - 1) / (2 * NLC), S.nz(), c_in);
-    TOF_LAUNCH((k_xf_reg<R, L, E, NLC, LPT, HALF>), grid, dim3((NLC / LPT) * (L / E)), 0, st, mode, dsg, src, S,
-                       out, hx, (const cplx<R> *)plan.tw);
+    const XfArgs<R> a{{}, mode, dsg, src, S, out, hx, (const cplx<R> *)plan.tw};
+    TOF_LAUNCH_B((k_xf_reg<R, L, E, NLC, LPT, HALF>), (k_xf_reg_batch<R, L, E, NLC, LPT, HALF>), grid,
+                 dim3((NLC / LPT) * (L / E)), st, a, mode, dsg, src, S, out, hx, (const cplx<R> *)plan.tw);
     return hipGetLastError();
 }
 
 // Design sources whose rows fill exactly x in [0, L/2) take the HALF form.
 template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
-                         const FftPlanDev &plan, cplx<R> *out, int hx)
+                         const FftPlanDev &plan, cplx<R> *out, int hx, int xtile)
 {
     const int xl = S.x0 > dsg.design.x0 ? S.x0 : dsg.design.x0;
     const int xh = S.x1 < dsg.design.x1 ? S.x1 : dsg.design.x1;
     const bool half = mode != SRC_ARRAY && xl == 0 && xh == L / 2 && dsg.nx == L / 2;
-    if (half) return launch_xf_reg_h<R, L, NLC, LPT, true>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    return launch_xf_reg_h<R, L, NLC, LPT, false>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    if (half) return launch_xf_reg_h<R, L, NLC, LPT, true>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    return launch_xf_reg_h<R, L, NLC, LPT, false>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
 }
 
 template <typename R>
 hipError_t launch_x_forward(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src,
-                            Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx)
+                            Box S, int c_in, const FftPlanDev &plan, cplx<R> *out, int hx, int xtile)
 {
     switch (plan.L) {
-    case 32: return launch_xf_reg<R, 32, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 64: return launch_xf_reg<R, 64, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 128: return launch_xf_reg<R, 128, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx);
-    case 256: return launch_xf_reg<R, 256, TOF_XF_NLC256, TOF_XF_LPT256>(st, mode, dsg, src, S, c_in, plan, out, hx);
+    case 32: return launch_xf_reg<R, 32, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    case 64: return launch_xf_reg<R, 64, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    case 128: return launch_xf_reg<R, 128, 16, 1>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    case 256: return launch_xf_reg<R, 256, TOF_XF_NLC256, TOF_XF_LPT256>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
     case 512:
         if constexpr (sizeof(R) == 8)
             return launch_xf_reg<R, 512, TOF_XF_NLC512_F64, TOF_XF_LPT512_F64>(st, mode, dsg, src, S, c_in, plan, out,
-                                                                             hx);
+                                                                             hx, xtile);
         else
-            return launch_xf_reg<R, 512, TOF_XF_NLC512, TOF_XF_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx);
+            return launch_xf_reg<R, 512, TOF_XF_NLC512, TOF_XF_LPT512>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
     default: break;
     }
     const int L = plan.L;
@@ -1943,12 +2034,13 @@ hipError_t launch_z_pass(hipStream_t st, cplx<R> *B, int hx, int Ly, int Zrows, 
 template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T, const FftPlanDev &plan,
                          bool grad_epilogue, View4<R> out, const DesignDev<R> &dsg, const R *m0u, R *grad, int zrows,
-                         int nsum, long long sum_stride)
+                         int nsum, long long sum_stride, int xtile)
 {
     constexpr int E = 8;
-    if ((long long)((T.ny() + 2 * NLC - 1) / (2 * NLC)) * T.nz() < 512 && NLC > 1)
+    const bool few = (long long)((T.ny() + 2 * NLC - 1) / (2 * NLC)) * T.nz() < 512;
+    if (NLC > 1 && (xtile == kXTilePair || (xtile == kXTileAuto && few)))
         return launch_xi_reg<R, L, 1, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum,
-                                         sum_stride);
+                                         sum_stride, xtile);
     const int gx = (T.ny() + 2 * NLC - 1) / (2 * NLC);
     // extra block rows for the zero fill, kZeroRowsPerBlock rows each
     const int gz = (int)((zrows + (long long)gx * kZeroRowsPerBlock - 1) / ((long long)gx * kZeroRowsPerBlock));
@@ -1957,9 +2049,12 @@ hipError_t launch_xi_reg(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
     // every stored column in the lower half of the line: the upper half of
     // the last stage and of the epilogue is never formed
     const bool half = T.x1 <= L / 2 && (!grad_epilogue || dsg.nx <= L / 2);
-#define TOF_XI_LAUNCH(CC, PSV, HV)                                                                               \
-    TOF_LAUNCH((k_xi_reg<R, L, E, NLC, LPT, CC, PSV, HV>), grid, block, 0, st, C, hx, T, grad_epilogue ? 1 : 0, out, \
-               dsg, m0u[0], m0u[1], m0u[2], grad, (const cplx<R> *)plan.tw, zrows, nsum, sum_stride)
+    const XiArgs<R> xa{{}, C, hx, T, grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad,
+                       (const cplx<R> *)plan.tw, zrows, nsum, sum_stride};
+#define TOF_XI_LAUNCH(CC, PSV, HV)                                                                    \
+    TOF_LAUNCH_B((k_xi_reg<R, L, E, NLC, LPT, CC, PSV, HV>), (k_xi_reg_batch<R, L, E, NLC, LPT, CC, PSV, HV>), \
+                 grid, block, st, xa, C, hx, T, grad_epilogue ? 1 : 0, out, dsg, m0u[0], m0u[1], m0u[2], grad,      \
+                 (const cplx<R> *)plan.tw, zrows, nsum, sum_stride)
 #define TOF_XI_LAUNCH_H(CC, PSV)                  \
     do {                                          \
         if (half) TOF_XI_LAUNCH(CC, PSV, true);   \
@@ -1979,7 +2074,7 @@ template <typename R>
 hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box T,
                             const FftPlanDev &plan, bool grad_epilogue, View4<R> out,
                             const DesignDev<R> &dsg, const R *m0u, R *grad, bool zero_outside, int nsum,
-                            long long sum_stride)
+                            long long sum_stride, int xtile)
 {
     if (nsum < 1) return hipErrorInvalidValue;
     const long long zr = grad_epilogue && zero_outside ? outside_rows(dsg.ny, dsg.nz, dsg.design) : 0;
@@ -1987,21 +2082,21 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
     const int zrows = (int)zr;
     if (c == 1 || c == 3) {
         switch (plan.L) {
-        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
-        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
+        case 32: return launch_xi_reg<R, 32, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride, xtile);
+        case 64: return launch_xi_reg<R, 64, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride, xtile);
         case 128:
-            return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride);
+            return launch_xi_reg<R, 128, 16, 1>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u, grad, zrows, nsum, sum_stride, xtile);
         case 256:
             return launch_xi_reg<R, 256, TOF_XI_NLC256, TOF_XI_LPT256>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
-                                                                    grad, zrows, nsum, sum_stride);
+                                                                    grad, zrows, nsum, sum_stride, xtile);
         case 512:
             if constexpr (sizeof(R) == 8)
                 return launch_xi_reg<R, 512, TOF_XI_NLC512_F64, TOF_XI_LPT512_F64>(st, C, hx, c, T, plan, grad_epilogue,
                                                                                  out, dsg, m0u, grad, zrows, nsum,
-                                                                                 sum_stride);
+                                                                                 sum_stride, xtile);
             else
                 return launch_xi_reg<R, 512, TOF_XI_NLC512, TOF_XI_LPT512>(st, C, hx, c, T, plan, grad_epilogue, out, dsg, m0u,
-                                                                    grad, zrows, nsum, sum_stride);
+                                                                    grad, zrows, nsum, sum_stride, xtile);
         default: break;
         }
     }
@@ -2042,8 +2137,9 @@ hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const F
 #define TOF_OBJ_CASE(LL)                                                                                     \
     case LL:                                                                                                 \
         if (check_only) return hipSuccess;                                                                   \
-        TOF_LAUNCH((k_objective_xf<R, LL, E>), grid, dim3(3 * (LL / E)), 0, st, o, A, hx, tw, spec, nsum,     \
-                   sum_stride, kx_fast ? 1 : 0);                                                             \
+        TOF_LAUNCH_B((k_objective_xf<R, LL, E>), (k_objective_xf_batch<R, LL, E>), grid, dim3(3 * (LL / E)), st, \
+                     (ObjXfArgs<R>{{}, o, A, hx, tw, spec, nsum, sum_stride, kx_fast ? 1 : 0}), o, A, hx, tw,   \
+                     spec, nsum, sum_stride, kx_fast ? 1 : 0);                                                  \
         return hipGetLastError();
     switch (plan.L) {
         TOF_OBJ_CASE(32)
@@ -2218,7 +2314,7 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
 
 #define TOF_INSTANTIATE(R)                                                                              \
     template hipError_t launch_x_forward<R>(hipStream_t, int, const DesignDev<R> &, View4<const R>, Box, \
-                                            int, const FftPlanDev &, cplx<R> *, int);                    \
+                                            int, const FftPlanDev &, cplx<R> *, int, int);               \
     template hipError_t launch_line_fft<R>(hipStream_t, const cplx<R> *, cplx<R> *, int, int, long long, \
                                            long long, long long, long long, int, int, int, int,          \
                                            const FftPlanDev &, bool, BlockMap, BlockMap);                \
@@ -2227,7 +2323,7 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                          const FftPlanDev &, BlockMap);                                  \
     template hipError_t launch_x_inverse<R>(hipStream_t, const cplx<R> *, int, int, Box,                 \
                                             const FftPlanDev &, bool, View4<R>, const DesignDev<R> &,    \
-                                            const R *, R *, bool, int, long long);                       \
+                                            const R *, R *, bool, int, long long, int);                  \
     template hipError_t launch_objective_xf<R>(hipStream_t, const ObjectiveDev<R> &, const FftPlanDev &,  \
                                                cplx<R> *, int, bool, const cplx<R> *, int, long long,     \
                                                bool);                                                     \

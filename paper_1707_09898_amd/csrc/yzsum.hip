@@ -112,6 +112,20 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
         }
 }
 
+// Arguments of the fused kernels (one design).
+template <typename R>
+struct YzKArgs {
+    BatchGrid bg;
+    const cplx<R> *A;
+    int hx, ys0, nys, zs0, nzs, zt0, nzt, rpg, yt0, nyt;
+    KtDev<R> kt;
+    ProductDev prod;
+    cplx<R> *out;          // gather: the partial rows; scatter: C
+    const cplx<R> *table;
+    int kxf;               // gather: partial rows with kx fastest
+    JFinal jf;             // scatter: J to form first, or none
+};
+
 // Few target rows.  Block (kx, g) takes source rows [g rpg, (g+1) rpg) of
 // the source box; line slot l transforms rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][nyt]
@@ -120,10 +134,8 @@ __device__ __forceinline__ void kt_full(const ProductDev &prod, int p, const R (
 // HALF: the source rows fill exactly the lower half of the line (ys0 = 0,
 // nys = L/2), so the loads need no bounds and the first stage skips the
 // zero half.
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
-    const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
-    KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF, typename BP>
+__device__ __forceinline__ void yzsum_gather_body(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt, const KtDev<R> &kt, const ProductDev &prod, cplx<R> *part, const cplx<R> *table, int kxf, const BP bp)
 {
     constexpr int P = L / E;
     constexpr int NL = kBlock / P;
@@ -135,8 +147,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
     __shared__ cplx<R> lds[NL * PITCH];
     const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
-    const int kx = blockIdx.x;
-    const int ra = blockIdx.y * rpg, rb = min(ra + rpg, nzs);
+    const int kx = bp.x();
+    const int ra = bp.y() * rpg, rb = min(ra + rpg, nzs);
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
     cplx<R> *my = lds + l * PITCH;
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
                 // every lane has read its sums before the first exchange write (one wave)
                 regfft::fft_line<R, L, E, true>(v, tw, lds, p, true);
                 // [g][o][kx][r][y], or [g][o][r][y][kx] (kx fastest)
-                const long long gbase = (long long)(blockIdx.y * CO + o) * hx * nzt * nyt;
+                const long long gbase = (long long)(bp.y() * CO + o) * hx * nzt * nyt;
                 const long long at0 = kxf ? gbase + (long long)r * nyt * hx + kx - (long long)yt0 * hx
                                           : gbase + ((long long)kx * nzt + r) * nyt - yt0;
                 const long long ys = kxf ? hx : 1;
@@ -224,6 +236,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
     }
 }
 
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
+    const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
+    KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
+{
+    yzsum_gather_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(A, hx, ys0, nys, zs0, nzs, zt0, nzt, rpg, yt0, nyt, kt, prod, part, table, kxf, HerePos{});
+}
+
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+{
+    BlockPos bp;
+    const YzKArgs<R> a = batch_args(tab, starts, n, bp);
+    yzsum_gather_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, a.kt, a.prod, a.out, a.table, a.kxf, bp);
+}
+
 // Few source rows.  Block (kx, g) takes target rows [g rpg, (g+1) rpg) of
 // the target box; line slot l handles rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys]; C is [CO][hx][nzt][nyt] with y from yt0 (the
@@ -231,13 +259,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 // HALF: the target rows fill exactly the lower half of the line (yt0 = 0,
 // nyt = L/2): the upper half of the inverse transform is never formed.
 // jf: J formed first by the first wave of block (0, 0) (see JFinal).
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs,
-                                                          int zt0, int nzt, int rpg, int yt0, int nyt, KtDev<R> kt,
-                                                          ProductDev prod, cplx<R> *C, const cplx<R> *table,
-                                                          JFinal jf)
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF, typename BP>
+__device__ __forceinline__ void yzsum_scatter_body(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt, const KtDev<R> &kt, const ProductDev &prod, cplx<R> *C, const cplx<R> *table, const JFinal &jf, const BP bp)
 {
-    if (jf.partials && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) finalize_j(jf);
+    if (jf.partials && bp.x() == 0 && bp.y() == 0 && threadIdx.x < 64) finalize_j(jf);
     constexpr int P = L / E;
     constexpr int NL = kBlock / P;
     constexpr int PITCH = regfft::padded_len(L);
@@ -248,7 +273,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
     __shared__ cplx<R> xs[NQ * L];   // source spectra, line q = r CI + i
     const int l = line_of_thread<P>();
     const int p = threadIdx.x % P;
-    const int kx = blockIdx.x;
+    const int kx = bp.x();
     cplx<R> tw[NT > 0 ? NT : 1];
     regfft::load_twiddles<R, L, E>(table, p, tw);
     cplx<R> *my = lds + l * PITCH;
@@ -271,7 +296,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
         }
     }
     __syncthreads();
-    const int ra = blockIdx.y * rpg, rb = min(ra + rpg, nzt);
+    const int ra = bp.y() * rpg, rb = min(ra + rpg, nzt);
     // slot l takes rows ra + l + NL (NV it + v), v < NV, per iteration it
     const int nit = (rb - ra + NV * NL - 1) / (NV * NL);
     constexpr int H = E / 2;
@@ -331,6 +356,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
     }
 }
 
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
+    const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
+    KtDev<R> kt, ProductDev prod, cplx<R> *C, const cplx<R> *table, JFinal jf)
+{
+    yzsum_scatter_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(A, hx, ys0, nys, zs0, nzs, zt0, nzt, rpg, yt0, nyt, kt, prod, C, table, jf, HerePos{});
+}
+
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+{
+    BlockPos bp;
+    const YzKArgs<R> a = batch_args(tab, starts, n, bp);
+    yzsum_scatter_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, a.kt, a.prod, a.out, a.table, a.jf, bp);
+}
+
 // Register and LDS limits of the fused kernels: the gather keeps NR x CO
 // accumulators per element, both keep NR x NC tensor values per element, the
 // scatter keeps NR x CI source spectra in LDS.
@@ -342,6 +383,20 @@ constexpr size_t scatter_lds(int L, int CI, int NR, size_t csz)
 constexpr bool scatter_fits(int L, int CI, int NC, int NR, size_t csz)
 {
     return NR * NC <= 6 && scatter_lds(L, CI, NR, csz) <= 96 * 1024;
+}
+
+template <typename R>
+YzKArgs<R> gather_args(const YzSumArgs<R> &a, const KtDev<R> &kt, const ProductDev &prod, const cplx<R> *table)
+{
+    return YzKArgs<R>{{}, a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part,
+                      table, a.part_kx_fast, JFinal{}};
+}
+
+template <typename R>
+YzKArgs<R> scatter_args(const YzSumArgs<R> &a, const KtDev<R> &kt, const ProductDev &prod, const cplx<R> *table)
+{
+    return YzKArgs<R>{{}, a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C,
+                      table, 0, a.jf};
 }
 
 template <typename R, int L, int CI, int CO, int NC, int PAR, bool HALF>
@@ -356,17 +411,19 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
         if (a.nzt == 1) {
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
-                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table,
-                           a.part_kx_fast);
+                TOF_LAUNCH_B((k_yzsum_gather<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
+                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), st,
+                             gather_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
+                             a.rpg, a.yt0, a.nyt, kt, prod, a.part, table, a.part_kx_fast);
                 return hipGetLastError();
             }
         } else {
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
-                TOF_LAUNCH((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                           a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.part, table,
-                           a.part_kx_fast);
+                TOF_LAUNCH_B((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
+                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), st,
+                             gather_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
+                             a.rpg, a.yt0, a.nyt, kt, prod, a.part, table, a.part_kx_fast);
                 return hipGetLastError();
             }
         }
@@ -375,17 +432,19 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     if (a.nzs == 1) {
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table,
-                               a.jf);
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), st,
+                         scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
+                         a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
         }
     } else if (a.nzs <= NRM) {
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), 0, st, a.A, a.hx,
-                               a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, kt, prod, a.C, table,
-                               a.jf);
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), st,
+                         scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
+                         a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
         }
     }

@@ -23,9 +23,12 @@ STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TO
 EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "tof_field",
            "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_project_step_static", "tof_tensor",
            "tof_padded_lengths", "tof_workspace_bytes", "tof_ctx_bytes", "tof_last_error", "tof_dd_newell_host",
-           "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option"]
+           "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option",
+           "tof_batch_create", "tof_batch_run", "tof_batch_launches", "tof_batch_destroy"]
 
 OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE = 1, 2, 3
+OPT_X_TILE, OPT_GATHER_GROUPS, OPT_SCATTER_GROUPS = 4, 5, 6
+X_TILE_AUTO, X_TILE_FULL, X_TILE_PAIR = 0, 1, 2
 GRID_SELFTEST_PERTURB = 1
 
 PROFILE_SLOTS = 12
@@ -93,9 +96,17 @@ def lib():
         L.tof_profile_kernel.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.tof_profile_kernel.restype = ctypes.c_char_p
         L.tof_set_option.argtypes = [vp, i32, i32]
+        L.tof_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       i32, ctypes.POINTER(vp)]
+        L.tof_batch_run.argtypes = [vp, vp]
+        L.tof_batch_launches.argtypes = [vp]
+        L.tof_batch_launches.restype = i32
+        L.tof_batch_destroy.argtypes = [vp]
+        L.tof_batch_destroy.restype = None
         for name in ("tof_create", "tof_set_design", "tof_set_objective", "tof_field",
                      "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_project_step_static",
-                     "tof_tensor", "tof_padded_lengths", "tof_profile_enable", "tof_profile_read", "tof_set_option"):
+                     "tof_tensor", "tof_padded_lengths", "tof_profile_enable", "tof_profile_read", "tof_set_option",
+                     "tof_batch_create", "tof_batch_run"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -240,9 +251,12 @@ class Engine:
             out.append((name, int(n.value)) if with_items else name)
         return out
 
-    def set_option(self, option: int, value: bool):
-        """Pass choice (OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE); see tof_set_option."""
-        self._check(lib().tof_set_option(self._ctx, int(option), 1 if value else 0))
+    def set_option(self, option: int, value):
+        """Pass choice (OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE: a bool) or
+        tile choice (OPT_X_TILE, OPT_GATHER_GROUPS, OPT_SCATTER_GROUPS: an
+        int); see tof_set_option."""
+        v = (1 if value else 0) if isinstance(value, bool) else int(value)
+        self._check(lib().tof_set_option(self._ctx, int(option), v))
 
     def padded_lengths(self) -> Tuple[int, int, int]:
         out = (ctypes.c_int32 * 3)()
@@ -252,6 +266,47 @@ class Engine:
     def ctx_bytes(self) -> int:
         """Device bytes the context holds (tof_ctx_bytes)."""
         return int(lib().tof_ctx_bytes(self._ctx))
+
+
+class Batch:
+    """tof_batch: one gradient evaluation of many designs with one launch per
+    pass and kernel instantiation (the engines' contexts and the rho, J, grad
+    tensors are borrowed and kept referenced here)."""
+
+    def __init__(self, engines, rho, J, grad):
+        n = len(engines)
+        vp = ctypes.c_void_p
+        arr = lambda xs: (vp * n)(*[vp(x) for x in xs])
+        self._refs = (list(engines), list(rho), list(J), list(grad))
+        self._b = vp()
+        for e, r, j, g in zip(engines, rho, J, grad):
+            e._arr(r, e.shape)
+            e._arr(g, e.shape)
+            e._arr(j, (1,), e.torch.float64)
+        st = lib().tof_batch_create(arr([e._ctx.value for e in engines]), arr([r.data_ptr() for r in rho]),
+                                    arr([j.data_ptr() for j in J]), arr([g.data_ptr() for g in grad]), n,
+                                    ctypes.byref(self._b))
+        if st != 0:
+            raise TofError(st, lib().tof_last_error(None).decode())
+
+    def run(self, stream=None):
+        st = lib().tof_batch_run(self._b, _stream_ptr(stream))
+        if st != 0:
+            raise TofError(st, lib().tof_last_error(None).decode())
+
+    def launches(self) -> int:
+        return int(lib().tof_batch_launches(self._b))
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib().tof_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def make_grid(n, h, dtype: str = "f32", L=None, validate: bool = False, flags: int = 0) -> Grid:

@@ -79,14 +79,16 @@ def torch():
 
 
 @pytest.mark.gpu
-def test_graph_replays_match_eager_launches(torch):
-    """Six designs of the 64-design batch on three streams: every replay of
-    the captured graph reproduces the eager results bit for bit, with other
-    device work and synchronizations between the replays."""
+@pytest.mark.parametrize("mode", ["batched", "streams"])
+def test_graph_replays_match_eager_launches(torch, mode):
+    """Six designs of the 64-design batch (batched launches, or each design's
+    own launches on three streams): every replay of the captured graph
+    reproduces the eager results bit for bit, with other device work and
+    synchronizations between the replays."""
     from paper_1707_09898_amd.batch import DesignBatch
     ws = smallest_designs(6)
-    say("batch graph", [w.n for w in ws])
-    b = DesignBatch(ws, "f32", streams=3)
+    say("batch graph", mode, [w.n for w in ws])
+    b = DesignBatch(ws, "f32", streams=3, mode=mode)
     b.run_eager()
     ref = b.results()
     b.capture()
@@ -108,8 +110,8 @@ def test_graph_replays_match_eager_launches(torch):
 @pytest.mark.gpu
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_batch_matches_oracle(torch, dtype, tol):
-    """The two smallest designs of the batch, evaluated by a graph replay,
-    against the oracle's J and full gradient."""
+    """The two smallest designs of the batch, evaluated by a graph replay of
+    the batched launches, against the oracle's J and full gradient."""
     from paper_1707_09898_amd.batch import DesignBatch
     ws = smallest_designs(2)
     b = DesignBatch(ws, dtype, streams=2)
@@ -162,7 +164,7 @@ def test_tuned_schedules_give_the_same_result(torch):
         assert best in times
         assert len(times) == len(autotune.candidate_triples(w.n)) * len(autotune.PASSES)
         sched.append(best)
-    b = DesignBatch(ws, "f64", [L for L, _ in sched], streams=2, passes=[p for _, p in sched])
+    b = DesignBatch(ws, "f64", [L for L, _ in sched], streams=2, passes=[p for _, p in sched], mode="streams")
     b.run_eager()
     got = b.results()
     b.close()
@@ -194,7 +196,7 @@ def test_whole_batch_with_tuned_schedules_matches_oracle(torch, oracle_cache):
     from paper_1707_09898_amd.batch import DesignBatch
     ws = wl.config5()
     sched = [autotune.tune_schedule(w, "f32", evals=2)[0] for w in ws]
-    b = DesignBatch(ws, "f32", [L for L, _ in sched], streams=4, passes=[p for _, p in sched])
+    b = DesignBatch(ws, "f32", [L for L, _ in sched], streams=4, passes=[p for _, p in sched], mode="streams")
     b.capture()
     b.replay()
     got = b.results()
@@ -207,3 +209,65 @@ def test_whole_batch_with_tuned_schedules_matches_oracle(torch, oracle_cache):
         worst = max(worst, eJ, eg)
         assert eJ <= 1e-5 and eg <= 1e-5, (i, w.name, sched[i], eJ, eg)
     say(f"batch: worst relative error over 64 designs {worst:.2e}")
+
+
+@pytest.mark.gpu
+def test_batched_form_whole_batch_matches_oracle_and_single_launches(torch, oracle_cache):
+    """All 64 designs in the batched form (one launch per pass and kernel
+    instantiation, over device tables of the designs' arguments), one graph
+    replay in FP32: J and the whole gradient of every design against the
+    oracle at 1e-5, and against the same design evaluated alone with the same
+    padded lengths (the same kernels: equal to rounding)."""
+    from paper_1707_09898_amd import tof
+    from paper_1707_09898_amd.batch import DesignBatch, batch_lengths
+    ws = wl.config5()
+    b = DesignBatch(ws, "f32")
+    n_launch = b.launches()
+    say(f"batched form: {n_launch} launches for {len(ws)} designs")
+    assert n_launch <= 5 * 12
+    b.capture()
+    b.replay()
+    got = b.results()
+    b.close()
+    ref = c5_reference(oracle_cache)
+    worst = 0.0
+    for i, (w, (J, g), (Jr, gr)) in enumerate(zip(ws, got, ref)):
+        eJ = abs(J - Jr) / abs(Jr)
+        eg = float(np.abs(g.astype(np.float64) - gr).max() / np.abs(gr).max())
+        worst = max(worst, eJ, eg)
+        assert eJ <= 1e-5 and eg <= 1e-5, (i, w.name, eJ, eg)
+    say(f"batched form: worst relative error over 64 designs {worst:.2e}")
+    for i in (0, 17, 63):
+        w = ws[i]
+        e = tof.engine_for(w, "f32", L=batch_lengths(w))
+        J1, g1 = e.objective_and_grad(torch.as_tensor(w.rho, dtype=torch.float32, device="cuda"))
+        torch.cuda.synchronize()
+        g1 = g1.cpu().numpy()
+        e.close()
+        J, g = got[i]
+        assert abs(J - J1.item()) <= 1e-6 * abs(J1.item())
+        assert np.abs(g - g1).max() <= 1e-6 * np.abs(g1).max()
+
+
+@pytest.mark.gpu
+def test_tuned_batched_form_matches_oracle(torch, oracle_cache):
+    """The tile knobs the batch tuner picks per padded length (x tile, gather
+    and scatter row groups) change only the work split (and the order of the
+    gather's partial sums): all 64 designs still match the oracle at 1e-5,
+    graph replays included."""
+    from paper_1707_09898_amd import autotune
+    from paper_1707_09898_amd.batch import DesignBatch
+    ws = wl.config5()
+    b = DesignBatch(ws, "f32")
+    table, best, trials = autotune.tune_batch(b, evals=3)
+    say(f"batch tuner: {best:.3f} ms, {len(trials)} trials, {table}")
+    assert set(table) == set(autotune.BATCH_KNOBS)
+    b.capture()
+    b.replay()
+    b.replay()
+    got = b.results()
+    b.close()
+    ref = c5_reference(oracle_cache)
+    for i, (w, (J, g), (Jr, gr)) in enumerate(zip(ws, got, ref)):
+        assert abs(J - Jr) <= 1e-5 * abs(Jr), (i, w.name)
+        assert np.abs(g.astype(np.float64) - gr).max() <= 1e-5 * np.abs(gr).max(), (i, w.name)
