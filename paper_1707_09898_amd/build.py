@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtof.so")
 
 SOURCES = ["kernels.hip", "yzsum.hip", "api.cpp"]
-HEADERS = ["dd.h", "fft.h", "fft_reg.h", "engine.h", "device_common.h"]
+HEADERS = ["dd.h", "fft.h", "fft_reg.h", "engine.h", "device_common.h", "body_xf_reg.inc", "body_xi_reg.inc",
+           "body_objective_xf.inc", "body_yzsum_gather.inc", "body_yzsum_scatter.inc"]
 
 # Packed FP32 instructions are kept out of every kernel (compiler option).
 HIPCC_FLAGS = [

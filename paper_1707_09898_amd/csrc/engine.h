@@ -128,30 +128,17 @@ struct YzSumArgs {
     JFinal jf;               // scatter: J to form first (block (0, 0), one wave), or none
 };
 
-// Block coordinates a pass kernel's body works on: its launch's own
-// (HerePos: blockIdx and gridDim, read where used), or, in a batched launch,
-// the block's place in the grid of its design (BlockPos).
+// In a batched launch, the block's place in the grid of its design.
 struct BlockPos {
     int x_, y_, z_;
     int gx_, gy_, gz_;
-    __device__ int x() const { return x_; }
-    __device__ int y() const { return y_; }
-    __device__ int z() const { return z_; }
-    __device__ int gx() const { return gx_; }
-    __device__ int gy() const { return gy_; }
-    __device__ int gz() const { return gz_; }
-};
-struct HerePos {
-    __device__ int x() const { return blockIdx.x; }
-    __device__ int y() const { return blockIdx.y; }
-    __device__ int z() const { return blockIdx.z; }
-    __device__ int gx() const { return gridDim.x; }
-    __device__ int gy() const { return gridDim.y; }
-    __device__ int gz() const { return gridDim.z; }
 };
 
 // Grid of one design's launch; the first member of every argument struct of
 // a kernel that can run batched (the batched launch reads it per design).
+// The kernels' bodies are in body_*.inc, included in the kernel that runs
+// one design and in the batched kernel, so each is compiled in its own
+// kernel's context.
 struct BatchGrid {
     int gx, gy, gz;
 };

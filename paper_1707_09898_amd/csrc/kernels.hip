@@ -712,174 +712,24 @@ __global__ __launch_bounds__(kObjThreads) void k_objective(int kind, const R *Hs
 // rows ty0 + 2l, ty0 + 2l + 1 back along x from their kx spectra (nsum
 // copies sum_stride apart, added in order; [cc][kx][zrel][y], or with kxf
 // [cc][zrel][y][kx]), so the field is never stored.
-template <typename R, int L, int E, typename BP>
-__device__ __forceinline__ void objective_xf_body(const ObjectiveDev<R> &o, cplx<R> *out, int hx, const cplx<R> *table, const cplx<R> *spec, int nsum, long long sum_stride, int kxf, const BP bp)
-{
-    constexpr int P = L / E;
-    constexpr int NLN = 3;
-    constexpr int NTH = NLN * P;
-    constexpr int HX = L / 2 + 1;
-    constexpr int PITCH = regfft::padded_len(L);
-    constexpr int AREA = PITCH > 2 * HX ? PITCH : 2 * HX;   // staging of a row pair's spectra, then the exchange
-    constexpr int NT = regfft::twiddle_count(L, E);
-    __shared__ cplx<R> lds[NLN * AREA];
-    constexpr int TR = 6;   // tile rows: the pair and two more on each side (the stencil's reach)
-    __shared__ R tile[TR * L];
-    const Box &ob = o.ob;
-    const int tid = threadIdx.x;
-    const int l = line_of_thread<P>();
-    const int p = tid % P;
-    const int cc = bp.z();
-    const int zrel = bp.y();
-    const int z = ob.z0 + zrel;
-    const int ybase = ob.y0 + 2 * bp.x();
-    const bool two = ybase + 1 < ob.y1;
-    cplx<R> tw[NT > 0 ? NT : 1];
-    regfft::load_twiddles<R, L, E>(table, p, tw);
-    // component cc of the field on rows ty0 .. ty1-1 of this z into LDS
-    const int ty0 = max(ob.y0, ybase - 2), ty1 = min(ob.y1, ybase + 4), nx = ob.nx();
-    {
-        cplx<R> *area = lds + l * AREA;
-        const int ya = min(ty0 + 2 * l, ty1 - 1), yb = min(ty0 + 2 * l + 1, ty1 - 1);
-        const int nyt = ob.ny(), nzt = ob.nz();
-        // the row pair's spectra [h][k] (h = 0: row ya, 1: row yb), copies
-        // added in order; with kx fastest a wave's loads cover whole rows
-        constexpr int NIT = (2 * HX + P - 1) / P;
-        const cplx<R> *base = spec;
-        cplx<R> w[NIT];
-        auto at = [&](int it) -> long long {
-            const int e = min(p + P * it, 2 * HX - 1);
-            const int h = e >= HX ? 1 : 0, k = e - h * HX;
-            const int yr = (h ? yb : ya) - ob.y0;
-            return kxf ? ((long long)(cc * nzt + zrel) * nyt + yr) * hx + k
-                       : ((long long)(cc * hx + k) * nzt + zrel) * nyt + yr;
-        };
-        // up to 8 copies per round, all their loads in flight together (the
-        // first round holds copy 0, so a few copies cost one memory latency)
-        constexpr int GU = 8;
-        for (int g0 = 0; g0 < nsum; g0 += GU) {
-            cplx<R> u[GU][NIT];
-#pragma unroll
-            for (int q = 0; q < GU; ++q) {
-                // copies past nsum issue no loads (a wave keeps at most 63
-                // loads in flight: more would cost a second memory latency)
-                if (g0 + q < nsum) {
-                    const cplx<R> *bg = base + (g0 + q) * sum_stride;
-#pragma unroll
-                    for (int it = 0; it < NIT; ++it) u[q][it] = bg[at(it)];
-                } else {
-#pragma unroll
-                    for (int it = 0; it < NIT; ++it) u[q][it] = cplx<R>{0, 0};
-                }
-            }
-#pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                cplx<R> acc = g0 == 0 ? u[0][it] : cadd(w[it], u[0][it]);
-#pragma unroll
-                for (int q = 1; q < GU; ++q)
-                    if (g0 + q < nsum) acc = cadd(acc, u[q][it]);
-                w[it] = acc;
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int e = p + P * it;
-            if (e < 2 * HX) area[e] = w[it];
-        }
-        regfft::exchange_sync<true>();
-        // two real rows in one complex line: Z = X_a + i X_b, X_b from the odd spectrum
-        cplx<R> v[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int k = p + P * m;
-            cplx<R> a, b;
-            if (k <= L / 2) {
-                a = area[k];
-                b = area[HX + k];
-                if (k == 0 || k == L / 2) {
-                    a.y = 0;
-                    b.y = 0;
-                }
-            } else {
-                a = cconj(area[L - k]);
-                b = cconj(area[HX + L - k]);
-            }
-            v[m] = cplx<R>{a.x - b.y, a.y + b.x};
-        }
-        regfft::exchange_sync<true>();
-        regfft::fft_line<R, L, E, true>(v, tw, area, p, true);
-        if (ty0 + 2 * l < ty1) {
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int x = p + P * m;
-                if (x < ob.x0 || x >= ob.x1) continue;
-                tile[(2 * l) * L + (x - ob.x0)] = v[m].x;
-                if (ty0 + 2 * l + 1 < ty1) tile[(2 * l + 1) * L + (x - ob.x0)] = v[m].y;
-            }
-        }
-    }
-    __syncthreads();
-    auto H = [&](int x, int y) -> double {
-        const int row = min(max(y, ty0), ty1 - 1) - ty0;
-        return (double)tile[row * L + min(max(x - ob.x0, 0), nx - 1)];
-    };
-    // dJ/dH on the pair's cells and their J terms, one cell per thread:
-    // cell e is row ybase + e / nx, column ob.x0 + e % nx
-    __shared__ R gpair[2 * L];
-    __shared__ double jslot[NLN];
-    double jsum = 0.0;
-    for (int e = tid; e < 2 * nx; e += NTH) {
-        const int h = e >= nx ? 1 : 0;
-        const int x = ob.x0 + e - h * nx;
-        double jt = 0.0, g = 0.0;
-        if (h == 0 || two) g = objective_cell(o, cc, x, ybase + h, z, H, jt);
-        jsum += jt;
-        gpair[h * L + x] = (R)g;
-    }
-    // the block's J terms: a butterfly over each slot's lanes, then the slots
-    // in order; the same order on every run
-    for (int w = P / 2; w > 0; w >>= 1) jsum += __shfl_xor(jsum, w, P);
-    if (p == 0) jslot[l] = jsum;
-    __syncthreads();
-    if (tid == 0) {
-        for (int s = 1; s < NLN; ++s) jsum += jslot[s];
-    }
-    if (l == 0) {
-        cplx<R> v[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int x = p + P * m;
-            const bool in = x >= ob.x0 && x < ob.x1;
-            v[m] = in ? cplx<R>{gpair[x], gpair[L + x]} : cplx<R>{0, 0};
-        }
-        regfft::fft_line<R, L, E, true>(v, tw, lds, p, false);
-#pragma unroll
-        for (int m = 0; m < E; ++m) lds[regfft::swz(p + P * m)] = v[m];
-    }
-    __syncthreads();
-    // split the pair: row y from the even part, row y + 1 from the odd part
-    const int nys = ob.ny(), nzs = ob.nz();
-    const long long kxs = (long long)nzs * nys;
-    cplx<R> *dst = out + (long long)cc * hx * kxs + (long long)zrel * nys + (ybase - ob.y0);
-    const R half = (R)0.5;
-    for (int e = tid; e < 2 * hx; e += NTH) {
-        const int k = e >> 1, r = e & 1;
-        if (r == 1 && !two) continue;
-        const cplx<R> Zk = lds[regfft::swz(k)];
-        const cplx<R> Zm = lds[regfft::swz((L - k) & (L - 1))];
-        dst[k * kxs + r] = r == 0 ? cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half}
-                                  : cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half};
-    }
-    // the block's J terms; J itself is formed from these by a later kernel
-    if (tid == 0) o.partials[(bp.z() * bp.gy() + bp.y()) * bp.gx() + bp.x()] = jsum;
-}
-
 template <typename R, int L, int E>
 __global__ __launch_bounds__(3 * (L / E)) void k_objective_xf(ObjectiveDev<R> o, cplx<R> *out, int hx,
                                                             const cplx<R> *table, const cplx<R> *spec, int nsum,
                                                             long long sum_stride, int kxf)
 {
-    objective_xf_body<R, L, E>(o, out, hx, table, spec, nsum, sum_stride, kxf, HerePos{});
+#define TOF_BX ((int)blockIdx.x)
+#define TOF_BY ((int)blockIdx.y)
+#define TOF_BZ ((int)blockIdx.z)
+#define TOF_BGX ((int)gridDim.x)
+#define TOF_BGY ((int)gridDim.y)
+#define TOF_BGZ ((int)gridDim.z)
+#include "body_objective_xf.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 template <typename R, int L, int E>
@@ -888,7 +738,27 @@ __global__ __launch_bounds__(3 * (L / E)) void k_objective_xf_batch(const ObjXfA
 {
     BlockPos bp;
     const ObjXfArgs<R> a = batch_args(tab, starts, n, bp);
-    objective_xf_body<R, L, E>(a.o, a.out, a.hx, a.table, a.spec, a.nsum, a.sum_stride, a.kxf, bp);
+    const auto &o = a.o;
+    const auto &out = a.out;
+    const auto &hx = a.hx;
+    const auto &table = a.table;
+    const auto &spec = a.spec;
+    const auto &nsum = a.nsum;
+    const auto &sum_stride = a.sum_stride;
+    const auto &kxf = a.kxf;
+#define TOF_BX (bp.x_)
+#define TOF_BY (bp.y_)
+#define TOF_BZ (bp.z_)
+#define TOF_BGX (bp.gx_)
+#define TOF_BGY (bp.gy_)
+#define TOF_BGZ (bp.gz_)
+#include "body_objective_xf.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 // One wave: J from the objective's block sums.
@@ -1424,136 +1294,23 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 // each thread transforms LPT of them in turn.  HALF (design sources only):
 // the design rows fill exactly the lower half of the line (x in [0, L/2)),
 // so the upper half is neither loaded nor transformed in the first stage.
-template <typename R, int L, int E, int NLC, int LPT, bool HALF, typename BP>
-__device__ __forceinline__ void xf_reg_body(int mode, const DesignDev<R> &dsg, const View4<const R> &src, const Box &S, cplx<R> *out, int hx, const cplx<R> *table, const BP bp)
-{
-    constexpr int ME = HALF ? E / 2 : E;   // slots that can hold data
-    constexpr int P = L / E;
-    constexpr int TY = 2 * NLC;
-    constexpr int PITCH = regfft::padded_len(L);
-    constexpr int NT = regfft::twiddle_count(L, E);
-    __shared__ cplx<R> lds[NLC * PITCH];
-    const int l0 = line_of_thread<P>();
-    const int p = threadIdx.x % P;
-    const int c = bp.z();
-    const int zrel = bp.y();
-    const int z = S.z0 + zrel;
-    const int ybase = S.y0 + bp.x() * TY;
-    const int nrow = min(TY, S.y1 - ybase);
-    cplx<R> tw[NT > 0 ? NT : 1];
-    regfft::load_twiddles<R, L, E>(table, p, tw);
-#pragma unroll
-    for (int j = 0; j < LPT; ++j) {
-        const int l = l0 + j * (NLC / LPT);
-        cplx<R> v[E];
-        const int r0 = 2 * l;
-        // row-level facts once; per element only the x range remains
-        const int yA = ybase + r0, yB = yA + 1;
-        const bool okA = r0 < nrow, okB = r0 + 1 < nrow;
-        if (!HALF && mode == SRC_ARRAY) {
-            const R *rowZ = src.ptr + c * src.cs + (long long)(z - src.oz) * src.zs - src.ox;
-            const R *rowA = rowZ + (long long)((okA ? yA : ybase) - src.oy) * src.ys;
-            const R *rowB = rowZ + (long long)((okB ? yB : ybase) - src.oy) * src.ys;
-            R ra[E], rb[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int xc = min(max(p + P * m, S.x0), S.x1 - 1);
-                ra[m] = rowA[xc];
-                rb[m] = rowB[xc];
-            }
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int x = p + P * m;
-                const bool in = x >= S.x0 && x < S.x1;
-                v[m] = cplx<R>{(in && okA) ? ra[m] : (R)0, (in && okB) ? rb[m] : (R)0};
-            }
-        } else {
-            const bool inA = okA && dsg.design.has(dsg.design.x0, yA, z);
-            const bool inB = okB && dsg.design.has(dsg.design.x0, yB, z);
-            const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
-            const long long offA = ((long long)z * dsg.ny + (okA ? yA : ybase)) * dsg.nx;
-            const long long offB = ((long long)z * dsg.ny + (okB ? yB : ybase)) * dsg.nx;
-            const R *rhoA = dsg.rho + offA, *rhoB = dsg.rho + offB;
-            const int xl = max(S.x0, dsg.design.x0), xh = min(S.x1, dsg.design.x1);
-            // every load from an address clamped into the row (with HALF all
-            // in it), all issued before the arithmetic; out-of-range
-            // elements are selected away
-            auto col = [&](int m) { return HALF ? p + P * m : min(p + P * m, dsg.nx - 1); };
-            R ra[ME], rb[ME], fa[ME], fb[ME];
-#pragma unroll
-            for (int m = 0; m < ME; ++m) {
-                ra[m] = rhoA[col(m)];
-                rb[m] = rhoB[col(m)];
-                fa[m] = fb[m] = (R)1;
-            }
-            if (mode == SRC_RHO_VECTOR) {
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    fa[m] = dsg.m0f[c * ncell + offA + col(m)];
-                    fb[m] = dsg.m0f[c * ncell + offB + col(m)];
-                }
-            }
-            if (dsg.mask) {
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    if (!dsg.mask[offA + col(m)]) fa[m] = 0;
-                    if (!dsg.mask[offB + col(m)]) fb[m] = 0;
-                }
-            }
-            ipow_n<R, ME>(ra, dsg.p);
-            ipow_n<R, ME>(rb, dsg.p);
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                if (m >= ME) {
-                    v[m] = cplx<R>{0, 0};
-                    continue;
-                }
-                const int x = p + P * m;
-                const bool in = HALF || (x >= xl && x < xh);
-                const R a = (in && inA) ? ra[m] * fa[m] : (R)0;
-                const R b = (in && inB) ? rb[m] * fb[m] : (R)0;
-                v[m] = cplx<R>{a, b};
-            }
-        }
-        cplx<R> *my = lds + l * PITCH;
-        regfft::fft_line<R, L, E, true, HALF>(v, tw, my, p, false);
-        // natural-order spectrum of the line into LDS (its own slot)
-#pragma unroll
-        for (int m = 0; m < E; ++m) my[regfft::swz(p + P * m)] = v[m];
-    }
-    __syncthreads();
-    // split the pairs and store TY consecutive y per kx
-    const int nys = S.ny(), nzs = S.nz();
-    const long long kxs = (long long)nzs * nys;
-    cplx<R> *o = out + (long long)c * hx * kxs + (long long)zrel * nys + (ybase - S.y0);
-    const R half = (R)0.5;
-    // thread: one row r, frequencies k0, k0 + KSTEP, ...
-    constexpr int NTH = (NLC / LPT) * P;
-    constexpr int KSTEP = NTH / TY;
-    constexpr int NIT = (L / 2 + 1 + KSTEP - 1) / KSTEP;
-    static_assert(NTH % TY == 0, "whole rows per sweep");
-    const int r = threadIdx.x % TY, k0 = threadIdx.x / TY;
-    if (r >= nrow) return;
-    const cplx<R> *line = lds + (r >> 1) * PITCH;
-    const bool odd = r & 1;
-    cplx<R> *op = o + (long long)k0 * kxs + r;
-    const long long ostep = (long long)KSTEP * kxs;
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int k = k0 + it * KSTEP;
-        if (k >= hx) break;
-        const cplx<R> Zk = line[regfft::swz(k)];
-        const cplx<R> Zm = line[regfft::swz((L - k) & (L - 1))];
-        op[it * ostep] = odd ? cplx<R>{(Zk.y + Zm.y) * half, (Zm.x - Zk.x) * half}
-                             : cplx<R>{(Zk.x + Zm.x) * half, (Zk.y - Zm.y) * half};
-    }
-}
-
 template <typename R, int L, int E, int NLC, int LPT, bool HALF>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
                                                                 Box S, cplx<R> *out, int hx, const cplx<R> *table)
 {
-    xf_reg_body<R, L, E, NLC, LPT, HALF>(mode, dsg, src, S, out, hx, table, HerePos{});
+#define TOF_BX ((int)blockIdx.x)
+#define TOF_BY ((int)blockIdx.y)
+#define TOF_BZ ((int)blockIdx.z)
+#define TOF_BGX ((int)gridDim.x)
+#define TOF_BGY ((int)gridDim.y)
+#define TOF_BGZ ((int)gridDim.z)
+#include "body_xf_reg.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 template <typename R, int L, int E, int NLC, int LPT, bool HALF>
@@ -1562,218 +1319,51 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
 {
     BlockPos bp;
     const XfArgs<R> a = batch_args(tab, starts, n, bp);
-    xf_reg_body<R, L, E, NLC, LPT, HALF>(a.mode, a.dsg, a.src, a.S, a.out, a.hx, a.table, bp);
+    const auto &mode = a.mode;
+    const auto &dsg = a.dsg;
+    const auto &src = a.src;
+    const auto &S = a.S;
+    const auto &out = a.out;
+    const auto &hx = a.hx;
+    const auto &table = a.table;
+#define TOF_BX (bp.x_)
+#define TOF_BY (bp.y_)
+#define TOF_BZ (bp.z_)
+#define TOF_BGX (bp.gx_)
+#define TOF_BGY (bp.gy_)
+#define TOF_BGZ (bp.gz_)
+#include "body_xf_reg.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 // -- pass 5: complex-to-real inverse FFT along x + epilogue -----------------
 // Block: NLC complex lines = 2 NLC target rows of one z, all CO components;
 // each thread transforms LPT lines in turn.  HALF: every column the pass
 // stores lies in the lower half of the line (x < L/2).
-template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF, typename BP>
-__device__ __forceinline__ void xi_reg_body(const cplx<R> *C, int hx, const Box &T, int grad_epi, const View4<R> &out, const DesignDev<R> &dsg, R m0u0, R m0u1, R m0u2, R *grad, const cplx<R> *table, int zrows, int nsum, long long sum_stride, const BP bp)
-{
-    if ((int)bp.y() >= T.nz()) {
-        // blocks past the target rows zero the gradient rows outside the design
-        // box (T is the design box then); the whole block leaves here
-        const int q0 = ((bp.y() - T.nz()) * bp.gx() + bp.x()) * kZeroRowsPerBlock;
-        for (int j = 0; j < kZeroRowsPerBlock && q0 + j < zrows; ++j) {
-            int y, z;
-            outside_row(q0 + j, dsg.ny, dsg.design, y, z);
-            R *row = grad + ((long long)z * dsg.ny + y) * dsg.nx;
-            for (int x = threadIdx.x; x < dsg.nx; x += blockDim.x) row[x] = (R)0;
-        }
-        return;
-    }
-    constexpr int ME = HALF ? E / 2 : E;   // output slots that can be stored
-    constexpr int P = L / E;
-    constexpr int TY = 2 * NLC;
-    constexpr int PITCH = regfft::padded_len(L);
-    constexpr int HX = L / 2 + 1;
-    constexpr int NT = regfft::twiddle_count(L, E);
-    constexpr int NLDS = TY * HX > NLC * PITCH ? TY * HX : NLC * PITCH;   // staging or exchange
-    __shared__ cplx<R> lds[NLDS];
-    const int l0 = line_of_thread<P>();
-    const int p = threadIdx.x % P;
-    const int zrel = bp.y();
-    const int z = T.z0 + zrel;
-    const int ybase = T.y0 + bp.x() * TY;
-    const int nrow = min(TY, T.y1 - ybase);
-    const int nyt = T.ny(), nzt = T.nz();
-    cplx<R> tw[NT > 0 ? NT : 1];
-    regfft::load_twiddles<R, L, E>(table, p, tw);
-    const R m0u[3] = {m0u0, m0u1, m0u2};
-    const long long ncell = (long long)dsg.nx * dsg.ny * dsg.nz;
-    R acc[LPT][2][E];
-#pragma unroll
-    for (int j = 0; j < LPT; ++j)
-#pragma unroll
-        for (int m = 0; m < E; ++m) acc[j][0][m] = acc[j][1][m] = 0;
-#pragma unroll
-    for (int cc = 0; cc < CO; ++cc) {
-        // stage the half spectra of the TY rows as [r][k]: all loads first
-        // (a batch of registers), then the LDS stores
-        // thread: one row r, frequencies k0, k0 + KSTEP, ...
-        constexpr int NTH = (NLC / LPT) * P;
-        constexpr int KSTEP = NTH / TY;
-        constexpr int NIT = (HX + KSTEP - 1) / KSTEP;
-        static_assert(NTH % TY == 0, "whole rows per sweep");
-        const int r = threadIdx.x % TY, k0 = threadIdx.x / TY;
-        const cplx<R> *src = C + ((long long)(cc * hx + k0) * nzt + zrel) * nyt + (ybase - T.y0 + min(r, nrow - 1));
-        const long long sstep = (long long)KSTEP * nzt * nyt;
-        cplx<R> stg[NIT];
-        const int itmax = (hx - 1 - k0) / KSTEP;   // rows past nrow and frequencies past hx read a clamped address
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) stg[it] = src[min(it, itmax) * sstep];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int k = k0 + it * KSTEP;
-            if (k < HX) lds[r * HX + k] = (r < nrow) ? stg[it] : cplx<R>{0, 0};
-        }
-        // partial copies of the input (PS), added in order in LDS (each thread
-        // updates only its own elements)
-        // up to 8 copies per round, all their loads in flight together
-        constexpr int GU = PS ? 8 : 1;
-        for (int g0 = 1; PS && g0 < nsum; g0 += GU) {
-            cplx<R> w[GU][NIT];
-#pragma unroll
-            for (int u = 0; u < GU; ++u) {
-                // copies past nsum issue no loads (at most 63 in flight a wave)
-                if (g0 + u < nsum) {
-                    const cplx<R> *sg = src + (g0 + u) * sum_stride;
-#pragma unroll
-                    for (int it = 0; it < NIT; ++it) w[u][it] = sg[min(it, itmax) * sstep];
-                } else {
-#pragma unroll
-                    for (int it = 0; it < NIT; ++it) w[u][it] = cplx<R>{0, 0};
-                }
-            }
-#pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                const int k = k0 + it * KSTEP;
-                if (k < HX && r < nrow) {
-                    cplx<R> acc = lds[r * HX + k];
-#pragma unroll
-                    for (int u = 0; u < GU; ++u)
-                        if (g0 + u < nsum) acc = cadd(acc, w[u][it]);
-                    lds[r * HX + k] = acc;
-                }
-            }
-        }
-        __syncthreads();
-        cplx<R> v[LPT][E];
-#pragma unroll
-        for (int j = 0; j < LPT; ++j) {
-            const int rA = 2 * (l0 + j * (NLC / LPT)), rB = rA + 1;
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int k = p + P * m;
-                cplx<R> a, b;
-                if (k <= L / 2) {
-                    a = lds[rA * HX + k];
-                    b = lds[rB * HX + k];
-                    if (k == 0 || k == L / 2) {
-                        a.y = 0;
-                        b.y = 0;
-                    }
-                } else {
-                    a = cconj(lds[rA * HX + (L - k)]);
-                    b = cconj(lds[rB * HX + (L - k)]);
-                }
-                v[j][m] = cplx<R>{a.x - b.y, a.y + b.x};
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < LPT; ++j) {
-            const int l = l0 + j * (NLC / LPT);
-            regfft::fft_line<R, L, E, true>(v[j], tw, lds + l * PITCH, p, true);
-        }
-        __syncthreads();   // the next component restages into the same LDS
-#pragma unroll
-        for (int j = 0; j < LPT; ++j) {
-            const int l = l0 + j * (NLC / LPT);
-            if (!grad_epi) {
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    const int x = p + P * m;
-                    if (x < T.x0 || x >= T.x1) continue;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int r = 2 * l + h;
-                        if (r >= nrow) continue;
-                        const int y = ybase + r;
-                        out.ptr[cc * out.cs + (long long)(z - out.oz) * out.zs + (long long)(y - out.oy) * out.ys +
-                                (x - out.ox)] = h ? v[j][m].y : v[j][m].x;
-                    }
-                }
-            } else if (dsg.m0f) {
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    // columns past nx accumulate a clamped value and are never stored
-                    const int xc = min(p + P * m, dsg.nx - 1);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int y = min(ybase + 2 * l + h, dsg.ny - 1);
-                        acc[j][h][m] += dsg.m0f[cc * ncell + ((long long)z * dsg.ny + y) * dsg.nx + xc] *
-                                        (h ? v[j][m].y : v[j][m].x);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    acc[j][0][m] += m0u[cc] * v[j][m].x;
-                    acc[j][1][m] += m0u[cc] * v[j][m].y;
-                }
-            }
-        }
-    }
-    if (grad_epi) {
-        // whole x rows: p rho^(p-1) acc inside the design region, zero elsewhere
-        const int xl = max(T.x0, dsg.design.x0), xh = min(T.x1, dsg.design.x1);
-#pragma unroll
-        for (int j = 0; j < LPT; ++j) {
-            const int l = l0 + j * (NLC / LPT);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int r = 2 * l + h;
-                if (r >= nrow) continue;
-                const int y = ybase + r;
-                const bool rowin = dsg.design.has(dsg.design.x0, y, z);
-                const long long off = ((long long)z * dsg.ny + y) * dsg.nx;
-                const R *rho = dsg.rho + off;
-                R *gr = grad + off;
-                R rv[ME];
-                bool mk[ME];
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    rv[m] = rho[min(p + P * m, dsg.nx - 1)];
-                    mk[m] = true;
-                }
-                if (dsg.mask) {
-#pragma unroll
-                    for (int m = 0; m < ME; ++m) mk[m] = dsg.mask[off + min(p + P * m, dsg.nx - 1)] != 0;
-                }
-                ipow_n<R, ME>(rv, dsg.p - 1);
-#pragma unroll
-                for (int m = 0; m < ME; ++m) {
-                    const int x = p + P * m;
-                    if (x >= dsg.nx) continue;
-                    R g = 0;
-                    if (rowin && x >= xl && x < xh && mk[m]) g = (R)dsg.p * rv[m] * acc[j][h][m];
-                    gr[x] = g;
-                }
-            }
-        }
-    }
-}
-
 template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(CO == 1 && !PS ? (sizeof(R) == 8 ? TOF_XI_WAVES_F64 : TOF_XI_WAVES) : 1))) void k_xi_reg(const cplx<R> *C, int hx, Box T, int grad_epi,
                                                                 View4<R> out, DesignDev<R> dsg, R m0u0, R m0u1,
                                                                 R m0u2, R *grad, const cplx<R> *table, int zrows,
                                                                 int nsum, long long sum_stride)
 {
-    xi_reg_body<R, L, E, NLC, LPT, CO, PS, HALF>(C, hx, T, grad_epi, out, dsg, m0u0, m0u1, m0u2, grad, table, zrows, nsum, sum_stride, HerePos{});
+#define TOF_BX ((int)blockIdx.x)
+#define TOF_BY ((int)blockIdx.y)
+#define TOF_BZ ((int)blockIdx.z)
+#define TOF_BGX ((int)gridDim.x)
+#define TOF_BGY ((int)gridDim.y)
+#define TOF_BGZ ((int)gridDim.z)
+#include "body_xi_reg.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 template <typename R, int L, int E, int NLC, int LPT, int CO, bool PS, bool HALF>
@@ -1782,7 +1372,33 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
 {
     BlockPos bp;
     const XiArgs<R> a = batch_args(tab, starts, n, bp);
-    xi_reg_body<R, L, E, NLC, LPT, CO, PS, HALF>(a.C, a.hx, a.T, a.grad_epi, a.out, a.dsg, a.m0u0, a.m0u1, a.m0u2, a.grad, a.table, a.zrows, a.nsum, a.sum_stride, bp);
+    const auto &C = a.C;
+    const auto &hx = a.hx;
+    const auto &T = a.T;
+    const auto &grad_epi = a.grad_epi;
+    const auto &out = a.out;
+    const auto &dsg = a.dsg;
+    const auto &m0u0 = a.m0u0;
+    const auto &m0u1 = a.m0u1;
+    const auto &m0u2 = a.m0u2;
+    const auto &grad = a.grad;
+    const auto &table = a.table;
+    const auto &zrows = a.zrows;
+    const auto &nsum = a.nsum;
+    const auto &sum_stride = a.sum_stride;
+#define TOF_BX (bp.x_)
+#define TOF_BY (bp.y_)
+#define TOF_BZ (bp.z_)
+#define TOF_BGX (bp.gx_)
+#define TOF_BGY (bp.gy_)
+#define TOF_BGZ (bp.gz_)
+#include "body_xi_reg.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 // ---- launch configuration helpers ----

@@ -134,114 +134,24 @@ struct YzKArgs {
 // HALF: the source rows fill exactly the lower half of the line (ys0 = 0,
 // nys = L/2), so the loads need no bounds and the first stage skips the
 // zero half.
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF, typename BP>
-__device__ __forceinline__ void yzsum_gather_body(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt, const KtDev<R> &kt, const ProductDev &prod, cplx<R> *part, const cplx<R> *table, int kxf, const BP bp)
-{
-    constexpr int P = L / E;
-    constexpr int NL = kBlock / P;
-    constexpr int PITCH = regfft::padded_len(L);
-    constexpr int NT = regfft::twiddle_count(L, E);
-    // a line that is a whole wave runs its own trip count; lines sharing a
-    // wave run the same count, a row past the range transforming zeros
-    constexpr bool EXACT = P == 64;
-    __shared__ cplx<R> lds[NL * PITCH];
-    const int l = line_of_thread<P>();
-    const int p = threadIdx.x % P;
-    const int kx = bp.x();
-    const int ra = bp.y() * rpg, rb = min(ra + rpg, nzs);
-    cplx<R> tw[NT > 0 ? NT : 1];
-    regfft::load_twiddles<R, L, E>(table, p, tw);
-    cplx<R> *my = lds + l * PITCH;
-    cplx<R> acc[NR][E][CO];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int m = 0; m < E; ++m)
-#pragma unroll
-            for (int o = 0; o < CO; ++o) acc[r][m][o] = cplx<R>{0, 0};
-    const int nit = EXACT ? (rb - ra > l ? (rb - ra - l + NL - 1) / NL : 0) : (rb - ra + NL - 1) / NL;
-    constexpr int H = E / 2;
-    for (int it = 0; it < nit; ++it) {
-        const int zr = ra + it * NL + l;
-        const bool ok = EXACT || zr < rb;
-        const int zrc = EXACT ? zr : min(zr, rb - 1);
-        // tensor values (independent of the transform) and the lines, all loads first
-        // (fetching the next row ahead instead raises the register count and gains nothing)
-        R Kh[NR][H + 1][NC];
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            kt_half<R, L, E, NC, PAR>(kt, prod, kx, p, zt0 + min(r, nzt - 1) - (zs0 + zrc), Kh[r]);
-        cplx<R> X[CI][E];
-#pragma unroll
-        for (int i = 0; i < CI; ++i) {
-            const cplx<R> *row = A + ((long long)(i * hx + kx) * nzs + zrc) * nys;
-            if constexpr (HALF) {
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const cplx<R> a = m < H ? row[p + P * m] : cplx<R>{0, 0};
-                    X[i][m] = ok ? a : cplx<R>{0, 0};
-                }
-            } else {
-                load_line<R, L, E>(row, ys0, nys, p, ok, X[i]);
-            }
-        }
-        R K[NR][E][NC];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC, PAR>(prod, p, Kh[r], K[r]);
-#pragma unroll
-        for (int i = 0; i < CI; ++i) regfft::fft_line<R, L, E, true, HALF>(X[i], tw, my, p, false);
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            cplx<R> xm[CI];
-#pragma unroll
-            for (int i = 0; i < CI; ++i) xm[i] = X[i][m];
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (NR == 1 || r < nzt) zsum_mac<R, CI, CO, NC, PAR>(prod, K[r][m], xm, acc[r][m]);
-        }
-    }
-    // the slots' sums, added in slot order by the first slot, transformed
-    // back along y there: the group's partial rows of the target in y space
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        if (NR > 1 && r >= nzt) break;
-#pragma unroll
-        for (int o = 0; o < CO; ++o) {
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < E; ++m) my[p + P * m] = acc[r][m][o];
-            __syncthreads();
-            if (l == 0) {
-                cplx<R> v[E];
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    cplx<R> s = lds[p + P * m];
-                    for (int sl = 1; sl < NL; ++sl) s = cadd(s, lds[sl * PITCH + p + P * m]);
-                    v[m] = s;
-                }
-                // every lane has read its sums before the first exchange write (one wave)
-                regfft::fft_line<R, L, E, true>(v, tw, lds, p, true);
-                // [g][o][kx][r][y], or [g][o][r][y][kx] (kx fastest)
-                const long long gbase = (long long)(bp.y() * CO + o) * hx * nzt * nyt;
-                const long long at0 = kxf ? gbase + (long long)r * nyt * hx + kx - (long long)yt0 * hx
-                                          : gbase + ((long long)kx * nzt + r) * nyt - yt0;
-                const long long ys = kxf ? hx : 1;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int n = p + P * m;
-                    if (n >= yt0 && n < yt0 + nyt) part[at0 + n * ys] = v[m];
-                }
-            }
-        }
-    }
-}
-
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
 {
-    yzsum_gather_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(A, hx, ys0, nys, zs0, nzs, zt0, nzt, rpg, yt0, nyt, kt, prod, part, table, kxf, HerePos{});
+#define TOF_BX ((int)blockIdx.x)
+#define TOF_BY ((int)blockIdx.y)
+#define TOF_BZ ((int)blockIdx.z)
+#define TOF_BGX ((int)gridDim.x)
+#define TOF_BGY ((int)gridDim.y)
+#define TOF_BGZ ((int)gridDim.z)
+#include "body_yzsum_gather.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
@@ -249,7 +159,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 {
     BlockPos bp;
     const YzKArgs<R> a = batch_args(tab, starts, n, bp);
-    yzsum_gather_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, a.kt, a.prod, a.out, a.table, a.kxf, bp);
+    const auto &A = a.A;
+    const auto &hx = a.hx;
+    const auto &ys0 = a.ys0;
+    const auto &nys = a.nys;
+    const auto &zs0 = a.zs0;
+    const auto &nzs = a.nzs;
+    const auto &zt0 = a.zt0;
+    const auto &nzt = a.nzt;
+    const auto &rpg = a.rpg;
+    const auto &yt0 = a.yt0;
+    const auto &nyt = a.nyt;
+    const auto &kt = a.kt;
+    const auto &prod = a.prod;
+    const auto &part = a.out;
+    const auto &table = a.table;
+    const auto &kxf = a.kxf;
+#define TOF_BX (bp.x_)
+#define TOF_BY (bp.y_)
+#define TOF_BZ (bp.z_)
+#define TOF_BGX (bp.gx_)
+#define TOF_BGY (bp.gy_)
+#define TOF_BGZ (bp.gz_)
+#include "body_yzsum_gather.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 // Few source rows.  Block (kx, g) takes target rows [g rpg, (g+1) rpg) of
@@ -259,109 +197,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 // HALF: the target rows fill exactly the lower half of the line (yt0 = 0,
 // nyt = L/2): the upper half of the inverse transform is never formed.
 // jf: J formed first by the first wave of block (0, 0) (see JFinal).
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF, typename BP>
-__device__ __forceinline__ void yzsum_scatter_body(const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt, const KtDev<R> &kt, const ProductDev &prod, cplx<R> *C, const cplx<R> *table, const JFinal &jf, const BP bp)
-{
-    if (jf.partials && bp.x() == 0 && bp.y() == 0 && threadIdx.x < 64) finalize_j(jf);
-    constexpr int P = L / E;
-    constexpr int NL = kBlock / P;
-    constexpr int PITCH = regfft::padded_len(L);
-    constexpr int NT = regfft::twiddle_count(L, E);
-    constexpr int NQ = NR * CI;
-    constexpr int NV = TOF_YZ_ROWS;   // target rows a slot transforms together
-    __shared__ cplx<R> lds[NV * NL * PITCH];
-    __shared__ cplx<R> xs[NQ * L];   // source spectra, line q = r CI + i
-    const int l = line_of_thread<P>();
-    const int p = threadIdx.x % P;
-    const int kx = bp.x();
-    cplx<R> tw[NT > 0 ? NT : 1];
-    regfft::load_twiddles<R, L, E>(table, p, tw);
-    cplx<R> *my = lds + l * PITCH;
-    const int nq = nzs * CI;
-#pragma unroll
-    for (int b = 0; b < (NQ + NL - 1) / NL; ++b) {
-        const int q = b * NL + l;
-        const bool ok = q < nq;
-        // a line that is a whole wave with no source row skips the transform
-        // (lines sharing a wave transform zeros instead)
-        if (P == 64 && !ok) continue;
-        const int qc = min(q, nq - 1);
-        const int r = qc / CI, i = qc % CI;
-        cplx<R> v[E];
-        load_line<R, L, E>(A + ((long long)(i * hx + kx) * nzs + r) * nys, ys0, nys, p, ok, v);
-        regfft::fft_line<R, L, E, true>(v, tw, my, p, false);
-        if (ok) {
-#pragma unroll
-            for (int m = 0; m < E; ++m) xs[q * L + p + P * m] = v[m];
-        }
-    }
-    __syncthreads();
-    const int ra = bp.y() * rpg, rb = min(ra + rpg, nzt);
-    // slot l takes rows ra + l + NL (NV it + v), v < NV, per iteration it
-    const int nit = (rb - ra + NV * NL - 1) / (NV * NL);
-    constexpr int H = E / 2;
-    // the tensor values of iteration `it`, loaded one iteration ahead
-    R Kh[NV][NR][H + 1][NC];
-    auto fetch = [&](int it, R (*Kf)[NR][H + 1][NC]) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int zrc = min(ra + (NV * it + v) * NL + l, rb - 1);
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                kt_half<R, L, E, NC, PAR>(kt, prod, kx, p, zt0 + zrc - (zs0 + min(r, nzs - 1)), Kf[v][r]);
-        }
-    };
-    fetch(0, Kh);
-    for (int it = 0; it < nit; ++it) {
-        R K[NV][NR][E][NC];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int r = 0; r < NR; ++r) kt_full<R, L, E, NC, PAR>(prod, p, Kh[v][r], K[v][r]);
-        fetch(it + 1, Kh);   // unconditional: a conditional fetch would be waited for before the transforms
-#pragma unroll
-        for (int o = 0; o < CO; ++o) {
-            cplx<R> Y[NV][E];
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    cplx<R> out[CO];
-#pragma unroll
-                    for (int oo = 0; oo < CO; ++oo) out[oo] = cplx<R>{0, 0};
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        if (NR > 1 && r >= nzs) break;
-                        cplx<R> xm[CI];
-#pragma unroll
-                        for (int i = 0; i < CI; ++i) xm[i] = xs[(r * CI + i) * L + p + P * m];
-                        zsum_mac<R, CI, CO, NC, PAR>(prod, K[v][r][m], xm, out);
-                    }
-                    Y[v][m] = out[o];
-                }
-            regfft::fft_lines<R, L, E, NV, true>(Y, tw, my, NL * PITCH, p, true);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const int zr = ra + (NV * it + v) * NL + l;
-                if (zr < rb) {
-                    cplx<R> *dst = C + (((long long)o * hx + kx) * nzt + zr) * nyt - yt0;
-#pragma unroll
-                    for (int m = 0; m < E; ++m) {
-                        const int n = p + P * m;
-                        if (HALF ? m < H : (n >= yt0 && n < yt0 + nyt)) dst[n] = Y[v][m];
-                    }
-                }
-            }
-        }
-    }
-}
-
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *C, const cplx<R> *table, JFinal jf)
 {
-    yzsum_scatter_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(A, hx, ys0, nys, zs0, nzs, zt0, nzt, rpg, yt0, nyt, kt, prod, C, table, jf, HerePos{});
+#define TOF_BX ((int)blockIdx.x)
+#define TOF_BY ((int)blockIdx.y)
+#define TOF_BZ ((int)blockIdx.z)
+#define TOF_BGX ((int)gridDim.x)
+#define TOF_BGY ((int)gridDim.y)
+#define TOF_BGZ ((int)gridDim.z)
+#include "body_yzsum_scatter.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
@@ -369,7 +222,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 {
     BlockPos bp;
     const YzKArgs<R> a = batch_args(tab, starts, n, bp);
-    yzsum_scatter_body<R, L, E, CI, CO, NC, NR, PAR, HALF>(a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt, a.rpg, a.yt0, a.nyt, a.kt, a.prod, a.out, a.table, a.jf, bp);
+    const auto &A = a.A;
+    const auto &hx = a.hx;
+    const auto &ys0 = a.ys0;
+    const auto &nys = a.nys;
+    const auto &zs0 = a.zs0;
+    const auto &nzs = a.nzs;
+    const auto &zt0 = a.zt0;
+    const auto &nzt = a.nzt;
+    const auto &rpg = a.rpg;
+    const auto &yt0 = a.yt0;
+    const auto &nyt = a.nyt;
+    const auto &kt = a.kt;
+    const auto &prod = a.prod;
+    const auto &C = a.out;
+    const auto &table = a.table;
+    const auto &jf = a.jf;
+#define TOF_BX (bp.x_)
+#define TOF_BY (bp.y_)
+#define TOF_BZ (bp.z_)
+#define TOF_BGX (bp.gx_)
+#define TOF_BGY (bp.gy_)
+#define TOF_BGZ (bp.gz_)
+#include "body_yzsum_scatter.inc"
+#undef TOF_BX
+#undef TOF_BY
+#undef TOF_BZ
+#undef TOF_BGX
+#undef TOF_BGY
+#undef TOF_BGZ
 }
 
 // Register and LDS limits of the fused kernels: the gather keeps NR x CO

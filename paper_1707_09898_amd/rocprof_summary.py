@@ -63,7 +63,7 @@ def code_tokens(text: str) -> str:
 def source_hash() -> str:
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")) +
-                    glob.glob(os.path.join(CSRC, "*.cpp"))):
+                    glob.glob(os.path.join(CSRC, "*.inc")) + glob.glob(os.path.join(CSRC, "*.cpp"))):
         h.update(os.path.basename(p).encode())
         with open(p, encoding="utf-8") as f:
             h.update(code_tokens(f.read()).encode())
