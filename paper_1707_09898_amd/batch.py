@@ -30,14 +30,17 @@ def pow2_at_least(v: int, lo: int = 32) -> int:
     return p
 
 
-def batch_lengths(w) -> Tuple[int, int, int]:
+def batch_lengths(w, floor: int = 32) -> Tuple[int, int, int]:
     """Padded lengths for the batched form: the smallest powers of two
-    >= 2n - 1 along x and y (at least 32; the fused kernels' register
-    transforms), the library's rule along z (the fused passes sum along z
-    directly and never transform along it)."""
+    >= 2n - 1 along x and y, and at least `floor` (>= 32; the fused kernels'
+    register transforms), the library's rule along z (the fused passes sum
+    along z directly and never transform along it).  A higher floor puts
+    small designs into the launches of larger ones (fewer launches, more
+    bytes)."""
     from .autotune import default_length
     nx, ny, nz = w.n
-    return (pow2_at_least(2 * nx - 1), pow2_at_least(2 * ny - 1), default_length(nz))
+    lo = max(32, int(floor))
+    return (pow2_at_least(2 * nx - 1, lo), pow2_at_least(2 * ny - 1, lo), default_length(nz))
 
 
 def balance(cost: Sequence[float], nstreams: int) -> List[List[int]]:

@@ -68,6 +68,17 @@ def test_null_context_calls_fail_cleanly():
     assert L.tof_set_option(None, tof.OPT_FUSE_YZ, 1) == -1
     assert L.tof_profile_kernel(None, 0, None) == b""
     L.tof_destroy(None)
+    # the batched form: null arrays, no designs
+    out = ctypes.c_void_p()
+    assert L.tof_batch_create(None, None, None, None, 1, ctypes.byref(out)) == -1 and out.value is None
+    vp1 = (ctypes.c_void_p * 1)(None)
+    assert L.tof_batch_create(vp1, vp1, vp1, vp1, 0, ctypes.byref(out)) == -1
+    assert L.tof_batch_create(vp1, vp1, vp1, vp1, 1, None) == -1
+    assert L.tof_batch_run(None, None) == -1
+    assert L.tof_batch_launches(None) == 0
+    L.tof_batch_destroy(None)
+    # options: unknown option, values out of range
+    assert L.tof_set_option(None, tof.OPT_X_TILE, 1) == -1
 
 
 @pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (1.0, 1.0, 0.5), (0.7, 1.3, 2.0), (1.9, 0.55, 1.2)])

@@ -438,3 +438,64 @@ def test_gpu_device_target_field_equals_host(torch):
     J3, g3 = e.objective_and_grad(rho)
     torch.cuda.synchronize()
     assert torch.equal(J1, J3) and torch.equal(g1, g3)
+
+
+# ---------------------------------------------------------------- tile options, graphs
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_gpu_tile_options_do_not_change_the_result(torch, dtype):
+    """The x tile and the scatter's row groups change only the work split:
+    the gradient is the same bit for bit; the gather's row groups change the
+    order of its partial sums, so the gradient agrees to rounding."""
+    t = tof()
+    w = wl.small_random(49, n=(40, 48, 19), design=(0, 40, 0, 48, 0, 15), sensor=(12, 28, 14, 34, 18, 19))
+    e = t.engine_for(w, dtype, L=(128, 128, 40))
+    rho = dev(torch, w.rho, e.dtype)
+    J0, g0 = e.objective_and_grad(rho)
+    J0, g0 = J0.clone(), g0.clone()
+    for opt, vals in ((t.OPT_X_TILE, (1, 2, 0)), (t.OPT_SCATTER_GROUPS, (1, 3, 7, 0))):
+        for v in vals:
+            e.set_option(opt, v)
+            J, g = e.objective_and_grad(rho)
+            torch.cuda.synchronize()
+            assert torch.equal(g, g0) and torch.equal(J, J0), (opt, v)
+    for v in (1, 2, 5):
+        e.set_option(t.OPT_GATHER_GROUPS, v)
+        J, g = e.objective_and_grad(rho)
+        torch.cuda.synchronize()
+        tol = 1e-12 if dtype == "f64" else 2e-6
+        assert abs(J.item() - J0.item()) <= tol * abs(J0.item())
+        assert float((g - g0).abs().max()) <= tol * float(g0.abs().max())
+    with pytest.raises(t.TofError):
+        e.set_option(t.OPT_X_TILE, 3)
+    with pytest.raises(t.TofError):
+        e.set_option(t.OPT_GATHER_GROUPS, 65)
+
+
+def test_gpu_graph_replays_of_one_evaluation(torch):
+    """One gradient evaluation recorded into a graph: three replays, with
+    the program's own eager work and synchronizations between them, each
+    equal bit for bit to the eager evaluation (the hot calls record no
+    memset or host synchronization)."""
+    t = tof()
+    w = wl.config2()
+    e = t.engine_for(w, "f32")
+    rho = dev(torch, w.rho, torch.float32)
+    J_ref, g_ref = e.objective_and_grad(rho)
+    J_ref, g_ref = J_ref.clone(), g_ref.clone()
+    g = torch.empty_like(rho)
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(graph, stream=cap):
+        e.objective_and_grad(rho, g, J, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.fill_(float("nan"))
+        J.fill_(float("nan"))
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 3).sum().item()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(g, g_ref) and torch.equal(J, J_ref), k
