@@ -115,7 +115,33 @@ def cpu_baseline(w, repeats):
                       f"direct sum on all {w.design[5] - w.design[4]} design layers), FP64; median"}
 
 
-def full_field_measurement(torch, tof, w, steps, repeats):
+def slot_times(tof, e, call, steps, burst_launches, bursts):
+    """Per-slot timing of engine e's calls: `steps` calls with an event per
+    launch (prof: per slot (name, total ms, launches, bytes per launch);
+    kernels: per slot (kernel name, work items)), then `bursts` calls in which
+    every slot's pass is launched again `burst_launches` times back to back
+    with HIP events around the burst only (an event bound to each launch
+    lengthens it); burst_ms per slot: the median of the bursts' mean ms per
+    launch, 0.0 where no burst ran (no bursts asked for, or a pass that works
+    in place)."""
+    e.profile(True)
+    for _ in range(steps):
+        call()
+    prof = e.profile_read()
+    kernels = e.profile_kernels(with_items=True)
+    active = [i for i, (_, _, cnt, _) in enumerate(prof) if cnt > 0]
+    runs = []
+    for _ in range(bursts if burst_launches > 0 else 0):
+        e.profile_burst(active, burst_launches)
+        call()
+        runs.append(e.profile_burst_read())
+    e.profile_read()   # the per-launch records of the burst calls are not used
+    e.profile(False)
+    burst_ms = [median([r[i] for r in runs]) if runs else 0.0 for i in range(tof.PROFILE_SLOTS)]
+    return prof, kernels, burst_ms
+
+
+def full_field_measurement(torch, tof, w, steps, repeats, burst_launches=100, bursts=5):
     """The five-pass FFT pipeline at 256 x 256 x 128 FP32: (a) the field H_z
     of the whole grid (tof_field, FFTs along x, y and z with the tensor
     product per frequency), and (b) the gradient with FFTs along z (the
@@ -128,13 +154,9 @@ def full_field_measurement(torch, tof, w, steps, repeats):
     for _ in range(3):
         e.field(rho, comps=4, out=H)
     ms = median(timed_loops(torch, lambda: e.field(rho, comps=4, out=H), steps, repeats))
-    e.profile(True)
-    for _ in range(steps):
-        e.field(rho, comps=4, out=H)
-    prof = e.profile_read()
-    kernels = e.profile_kernels(with_items=True)
-    e.profile(False)
-    slots = [(i, name, t / c, c, by) for i, (name, t, c, by) in enumerate(prof) if c > 0]
+    prof, kernels, burst_ms = slot_times(tof, e, lambda: e.field(rho, comps=4, out=H), steps, burst_launches, bursts)
+    # mean launch time: the burst's, or with an event per launch for a pass that works in place
+    slots = [(i, name, burst_ms[i] or t / c, c, by) for i, (name, t, c, by) in enumerate(prof) if c > 0]
     pass_bytes = sum(by for (_, _, _, _, by) in slots)
     dom = max(slots, key=lambda s: s[2])
     model_f = model_bytes_per_field(w, 4, L)
@@ -146,6 +168,8 @@ def full_field_measurement(torch, tof, w, steps, repeats):
              "pass_bytes": pass_bytes, "pass_GBps": pass_bytes / (ms * 1e-3) / 1e9,
              "pass_frac": pass_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
              "per_kernel_us": {f"{name}:{kernels[i][0]}": round(avg * 1e3, 2) for (i, name, avg, _, _) in slots},
+             "per_kernel_timing": {f"{name}:{kernels[i][0]}": ("burst" if burst_ms[i] else "event per launch")
+                                   for (i, name, _, _, _) in slots},
              "dominant_kernel": {"kernel": kernels[dom[0]][0], "slot": dom[1], "avg_launch_us": dom[2] * 1e3,
                                  "bytes_per_launch": dom[4],
                                  "achieved_GBps": dom[4] / (dom[2] * 1e-3) / 1e9,
@@ -248,6 +272,9 @@ def main():
     ap.add_argument("--repeats", type=int, default=5, help="timed loops of --steps steps (median)")
     ap.add_argument("--no-full-field", action="store_true", help="skip the five-pass pipeline measurement")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--burst-launches", type=int, default=100,
+                    help="launches per burst of each pass for the per-kernel times (0: an event per launch)")
+    ap.add_argument("--bursts", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch measurement")
     ap.add_argument("--no-paths", action="store_true", help="skip timing the unfused pass choices")
     ap.add_argument("--batch-replays", type=int, default=20)
@@ -292,13 +319,8 @@ def main():
         ms = median(loops)
         J_main = float(J.item())
         grad_main = grad.double()   # the timed path's gradient, for the precision report
-        # per-launch timing in a second pass over the same number of steps
-        e.profile(True)
-        for _ in range(args.profile_steps):
-            e.objective_and_grad(rho, grad, J)
-        prof = e.profile_read()
-        kernels = e.profile_kernels(with_items=True)
-        e.profile(False)
+        prof, kernels, burst_ms = slot_times(tof, e, lambda: e.objective_and_grad(rho, grad, J),
+                                             args.profile_steps, args.burst_launches, args.bursts)
         paths = {}
         if dtype == "f32" and not args.no_paths:
             # the same evaluation on the other pass choices (direct z sum unfused; FFTs along z)
@@ -313,7 +335,7 @@ def main():
             for opt in (tof.OPT_ZSUM, tof.OPT_FUSE_YZ, tof.OPT_FUSE_OBJECTIVE):
                 e.set_option(opt, 1)
         results[dtype] = {"ms": ms, "loops": loops, "prof": prof, "kernels": kernels, "L": L, "J": J_main,
-                          "paths": paths}
+                          "paths": paths, "burst_ms": burst_ms}
         print(f"[bench] {dtype}: {ms:.4f} ms/eval, {1000.0 / ms:.1f} evals/s, J={J_main:.10e}",
               file=sys.stderr, flush=True)
         results[dtype]["grad"] = grad_main
@@ -323,7 +345,10 @@ def main():
     r32 = results["f32"]
     wsize = 4
     evals = 1000.0 / r32["ms"]
-    slots = [(name, ms_tot / cnt, cnt, by) for (name, ms_tot, cnt, by) in r32["prof"] if cnt > 0]
+    # per slot: (name, mean ms per launch, launches, algorithmic bytes per launch, ms with an event per launch);
+    # the mean launch time is the burst's where bursts ran
+    slots = [(name, r32["burst_ms"][i] or ms_tot / cnt, cnt, by, ms_tot / cnt)
+             for i, (name, ms_tot, cnt, by) in enumerate(r32["prof"]) if cnt > 0]
     dom = max(slots, key=lambda s: s[1])
     dom_idx = tof.PROFILE_NAMES.index(dom[0])
     dom_kernel, dom_items = r32["kernels"][dom_idx]
@@ -337,11 +362,11 @@ def main():
           "counter summary file not found: " + os.path.relpath(TRAFFIC_SUMMARY, ROOT)))
     if not same_src:
         traffic = None
-    pass_bytes = sum(by for (_, _, cnt, by) in slots)
+    pass_bytes = sum(s[3] for s in slots)
     model = model_bytes_per_eval(w, wsize, r32["L"])
     # measured traffic of the whole evaluation: every timed kernel's counters
     measured = 0.0
-    for (name, avg, cnt, by) in slots:
+    for (name, avg, cnt, by, _) in slots:
         kname, items = r32["kernels"][tof.PROFILE_NAMES.index(name)]
         tb, ok = rocprof_summary.lookup(TRAFFIC_SUMMARY, kname, "float", items)
         if tb is None or not ok:
@@ -390,8 +415,20 @@ def main():
                                 "note": "algorithmic bytes of the sensor-pruned passes; traffic = the counters "
                                         "(copy-calibrated FETCH_SIZE + WRITE_SIZE) of the same five kernels, "
                                         "null when the sources changed since they were taken"},
+        # mean launch time per kernel: a burst of back-to-back launches of its
+        # pass between two HIP events on its stream, median of the bursts
         "per_kernel_us": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)][0]}": round(avg * 1e3, 2)
-                          for (name, avg, _, _) in slots},
+                          for (name, avg, _, _, _) in slots},
+        "per_kernel_timing": (f"burst of {args.burst_launches} launches, median of {args.bursts}"
+                              if args.burst_launches > 0 else "an event per launch"),
+        # every kernel's algorithmic bytes per launch / its mean launch time, of the HBM peak
+        "per_kernel_frac": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)][0]}":
+                            round(by / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 3) for (name, avg, _, by, _) in slots},
+        "per_kernel_sum_us": round(sum(s[1] for s in slots) * 1e3, 2),
+        # the same launches inside the evaluation, each with its own completion
+        # event (the events lengthen every launch by a few microseconds)
+        "per_kernel_us_event_per_launch": {f"{name}:{r32['kernels'][tof.PROFILE_NAMES.index(name)][0]}":
+                                           round(ev * 1e3, 2) for (name, _, _, _, ev) in slots},
         "paths_f32_evals_per_s": dict({"fused": evals}, **r32["paths"]),
         "roofline": {"bound": "hbm", "kernel": f"{dom_kernel} ({dom[0]}, {dom_items} work items)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -399,7 +436,8 @@ def main():
                      "bytes_per_launch": dom[3], "avg_launch_us": dom[1] * 1e3},
     }
     if not args.no_full_field:
-        out["full_field_pipeline"] = full_field_measurement(torch, tof, w, max(10, args.steps // 2), args.repeats)
+        out["full_field_pipeline"] = full_field_measurement(torch, tof, w, max(10, args.steps // 2), args.repeats,
+                                                            args.burst_launches, args.bursts)
     if not args.no_batch:
         out["c5_batch"] = batch_measurement(torch, wl, args)
     if not args.no_cpu_baseline:

@@ -241,8 +241,27 @@ tof_status tof_project_step_static(const tof_grid *grid, const tof_box *design, 
 tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream);
 
 /*
+ * tof_tensor_full -- the same tensor at every signed offset, device double
+ * [6][2nz-1][2ny-1][2nx-1], entry (kz + nz - 1, ky + ny - 1, kx + nx - 1) for
+ * offset (kx, ky, kz), |k_a| < n_a: the octant of tof_tensor with the parity
+ * signs applied (the discrete tensor of eq. (demag_tensor) for every pair of
+ * cells of the grid).  Allocates temporaries and synchronizes.
+ * Errors: TOF_ERR_INVALID, TOF_ERR_OOM, TOF_ERR_HIP.
+ */
+tof_status tof_tensor_full(tof_ctx *ctx, double *N, void *stream);
+
+/*
  * Per-launch timing (a measurement aid).  While enabled, every hot call
- * brackets each kernel launch with HIP events on its launch stream.  Slots:
+ * times its kernel launches on their stream with HIP events: each launch
+ * carries a stop event that takes the kernel's completion timestamp
+ * (hipExtLaunchKernelGGL, no packet added to the stream).  A launch that
+ * directly follows a timed launch on the same stream (no other launch of the
+ * library in between) is timed from that launch's completion to its own,
+ * which is the launch's share of a back-to-back sequence; the first launch
+ * of such a chain is timed from an event recorded just before it, which adds
+ * that event's latency, and a slot reports those only when it has no chained
+ * launch.  A pass of several kernels is timed to an event recorded after its
+ * last one.  Slots:
  * 0-4 the passes of the forward convolution (x, y, z with the tensor product,
  * inverse y, inverse x with its epilogue), 5 the objective (with
  * TOF_OPT_FUSE_OBJECTIVE also the adjoint's x pass, slot 6 then unused), 6-10
@@ -267,6 +286,25 @@ tof_status tof_profile_enable(tof_ctx *ctx, int32_t enable);
  * TOF_ERR_HIP.
  */
 tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[], double bytes_host[]);
+
+/*
+ * Bursts (a measurement aid that adds nothing to a launch): with timing
+ * enabled, tof_profile_burst arms every slot whose bit is set in slot_mask;
+ * the next call that runs the slot's pass launches that pass `repeats` more
+ * times back to back right after its own launch, between two events on its
+ * stream, and disarms the slot.  Every repeated pass writes only its
+ * outputs, from inputs it leaves unchanged, so the call's results are those
+ * of a call without the burst; the z passes of the unfused paths work in
+ * place and are not repeated (their slots report 0).
+ * tof_profile_burst_read synchronizes and writes per slot the mean
+ * milliseconds per launch of its last burst (0 where none ran), then clears
+ * them.  repeats in [1, TOF_PROFILE_MAX_BURST].
+ * Errors: TOF_ERR_INVALID (timing off, repeats or mask out of range, null
+ * argument), TOF_ERR_HIP.
+ */
+#define TOF_PROFILE_MAX_BURST 4096
+tof_status tof_profile_burst(tof_ctx *ctx, uint32_t slot_mask, int32_t repeats);
+tof_status tof_profile_burst_read(tof_ctx *ctx, double ms_host[]);
 
 /*
  * Name of the kernel last timed in a slot (e.g. "k_yzsum_gather"), "" if

@@ -18,6 +18,9 @@
 thread_local const char *g_last_kernel = "";
 thread_local long long g_last_items = 0;
 thread_local std::vector<BatchLaunch> *g_batch_record = nullptr;
+thread_local hipEvent_t g_prof_stop = nullptr;
+thread_local int g_prof_launches = 0;
+thread_local unsigned long long g_launch_seq = 0;
 thread_local const char *g_batch_unbatchable = nullptr;
 
 namespace {
@@ -86,7 +89,19 @@ struct tof_ctx {
     // per-launch timing
     bool prof_on = false;
     int prof_calls[TOF_PROFILE_SLOTS] = {};
-    std::vector<hipEvent_t> prof_ev;   // [slot][call][2]
+    std::vector<hipEvent_t> prof_ev;     // [slot][call]: the launch's stop event
+    std::vector<hipEvent_t> prof_refs;   // chain anchors, recorded where a chain of launches starts
+    std::vector<int> prof_rec_ref;       // [slot][call]: the anchor of the launch's chain
+    std::vector<hipEvent_t> prof_rec_prev;   // [slot][call]: stop event of the launch before it, or null
+    int prof_nref = 0, prof_cur_ref = -1;
+    hipEvent_t prof_last = nullptr;      // stop event of the last timed launch
+    hipStream_t prof_last_st = nullptr;
+    unsigned long long prof_last_seq = 0;
+    // bursts: the pass of a slot launched again back to back, between two events
+    uint32_t prof_burst_mask = 0;
+    int prof_burst_reps = 0;
+    hipEvent_t prof_burst_ev[TOF_PROFILE_SLOTS][2] = {};
+    int prof_burst_done[TOF_PROFILE_SLOTS] = {};
     double prof_bytes[TOF_PROFILE_SLOTS] = {};
     std::string prof_kernel[TOF_PROFILE_SLOTS];
     long long prof_items[TOF_PROFILE_SLOTS] = {};
@@ -140,6 +155,7 @@ void batch_release(tof_batch *b)
 namespace {
 
 constexpr int kProfCalls = 1024;
+constexpr int kProfAnchors = 256;
 // largest |tr N(k) - delta_k0| the setup accepts (the FP64 tensor entries are
 // each within half an ulp of |N| <= 1 after the double-double evaluation)
 constexpr double kTraceTol = 1e-12;
@@ -172,19 +188,44 @@ tof_status hip_fail(tof_ctx *ctx, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
-// Launch through `fn` and, when timing is on, bracket it with events of the
-// slot on the same stream; `bytes` is the pass's algorithmic traffic.
+// Launch through `fn` and, when timing is on, time it.  The stop event of
+// the slot goes with the kernel launch (its completion timestamp,
+// hipExtLaunchKernelGGL), or is recorded after the last launch when `fn`
+// launches several.  A launch whose stream ran a timed launch just before it
+// (nothing launched in between) is timed from that launch's end to its own:
+// the two ends are read against the anchor of their chain, so no packet is
+// added between the kernels.  Where no such launch precedes, an anchor event
+// is recorded first and the launch is timed from it (that time also holds
+// the anchor's latency).  `bytes` is the pass's algorithmic traffic.
 template <typename F>
-hipError_t timed(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn)
+hipError_t timed_once(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn)
 {
     if (!ctx->prof_on || ctx->prof_calls[slot] >= kProfCalls) return fn();
-    hipEvent_t *ev = &ctx->prof_ev[((size_t)slot * kProfCalls + ctx->prof_calls[slot]) * 2];
-    hipError_t e = hipEventRecord(ev[0], st);
+    const size_t idx = (size_t)slot * kProfCalls + ctx->prof_calls[slot];
+    const bool chained = ctx->prof_last && ctx->prof_last_st == st && ctx->prof_last_seq == g_launch_seq;
+    if (!chained) {
+        if (ctx->prof_nref >= (int)ctx->prof_refs.size()) return fn();   // out of anchors: not timed
+        hipError_t e = hipEventRecord(ctx->prof_refs[ctx->prof_nref], st);
+        if (e != hipSuccess) return e;
+        ctx->prof_cur_ref = ctx->prof_nref++;
+    }
+    hipEvent_t stop = ctx->prof_ev[idx];
+    g_prof_stop = stop;
+    g_prof_launches = 0;
+    hipError_t e = fn();
+    const bool consumed = g_prof_stop == nullptr;
+    g_prof_stop = nullptr;
     if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(ev[1], st);
-    if (e != hipSuccess) return e;
+    if (!consumed) return hipSuccess;   // nothing was launched: nothing to time
+    if (g_prof_launches > 1) {
+        e = hipEventRecord(stop, st);
+        if (e != hipSuccess) return e;
+    }
+    ctx->prof_rec_ref[idx] = ctx->prof_cur_ref;
+    ctx->prof_rec_prev[idx] = chained ? ctx->prof_last : nullptr;
+    ctx->prof_last = stop;
+    ctx->prof_last_st = st;
+    ctx->prof_last_seq = g_launch_seq;
     ctx->prof_calls[slot]++;
     ctx->prof_bytes[slot] = bytes;
     // the launch expression, e.g. "(k_xi_reg<R, L, ...>)", reduced to the kernel's name
@@ -192,6 +233,26 @@ hipError_t timed(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn)
     if (!k.empty() && k[0] == '(') k = k.substr(1);
     ctx->prof_kernel[slot] = k.substr(0, k.find_first_of("<(), "));
     ctx->prof_items[slot] = g_last_items;
+    return hipSuccess;
+}
+
+// timed_once, then, when a burst is armed for the slot, the same pass again
+// prof_burst_reps times back to back between two events.  A repeatable pass
+// writes only its outputs, from inputs it does not change, so the repeats
+// leave the results as they are; a pass that works in place is not repeated.
+template <typename F>
+hipError_t timed(tof_ctx *ctx, hipStream_t st, int slot, double bytes, F fn, bool repeatable = true)
+{
+    hipError_t e = timed_once(ctx, st, slot, bytes, fn);
+    if (e != hipSuccess || !ctx->prof_on || !((ctx->prof_burst_mask >> slot) & 1u)) return e;
+    if (!repeatable) return hipSuccess;
+    ctx->prof_burst_mask &= ~(1u << slot);
+    hipEvent_t *bev = ctx->prof_burst_ev[slot];
+    if ((e = hipEventRecord(bev[0], st)) != hipSuccess) return e;
+    for (int r = 0; r < ctx->prof_burst_reps; ++r)
+        if ((e = fn()) != hipSuccess) return e;
+    if ((e = hipEventRecord(bev[1], st)) != hipSuccess) return e;
+    ctx->prof_burst_done[slot] = ctx->prof_burst_reps;
     return hipSuccess;
 }
 
@@ -482,11 +543,11 @@ tof_status convolve(tof_ctx *ctx, hipStream_t st, int slot0, int mode, const Des
         // few source or target rows: direct sum against the x-y transformed tensor
         HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + kt_bytes, [&] {
             return launch_z_sum<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), kt, prod, bm);
-        }));
+        }, false));
     } else {
         HIP_TRY(ctx, timed(ctx, st, slot0 + 2, (b_in + b_out) * cw + spec_bytes, [&] {
             return launch_z_pass<R>(st, B, hx, Ly, Zr, S.z0, S.nz(), T.z0, T.nz(), sp, prod, false, plz, bm);
-        }));
+        }, false));
     }
     HIP_TRY(ctx, timed(ctx, st, slot0 + 3, (b_out + c_elems) * cw, [&] {
         return launch_line_fft<R>(st, B, C, prod.c_out * hx * T.nz(), T.nz(), (long long)Zr * Ly, bm.row,
@@ -761,7 +822,15 @@ tof_status compute_spectra(tof_ctx *ctx, hipStream_t st)
 void release(tof_ctx *ctx)
 {
     for (hipEvent_t ev : ctx->prof_ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : ctx->prof_refs) (void)hipEventDestroy(ev);
+    for (auto &pair : ctx->prof_burst_ev)
+        for (hipEvent_t &ev : pair)
+            if (ev) {
+                (void)hipEventDestroy(ev);
+                ev = nullptr;
+            }
     ctx->prof_ev.clear();
+    ctx->prof_refs.clear();
     DeviceBuf *bufs[] = {&ctx->spec, &ctx->kt, &ctx->A, &ctx->B, &ctx->C, &ctx->Hs, &ctx->G, &ctx->Ht,
                          &ctx->scratch64, &ctx->steppart, &ctx->partials, &ctx->ticket};
     for (DeviceBuf *b : bufs)
@@ -1098,14 +1167,44 @@ tof_status tof_tensor(tof_ctx *ctx, double *N, void *stream)
     return TOF_OK;
 }
 
+tof_status tof_tensor_full(tof_ctx *ctx, double *N, void *stream)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (!N) return fail(ctx, TOF_ERR_INVALID, "N is null");
+    hipStream_t st = (hipStream_t)stream;
+    DeviceBuf oct;
+    tof_status s = dev_alloc(ctx, oct, sizeof(double) * 6 * (size_t)ctx->nx * ctx->ny * ctx->nz);
+    if (s != TOF_OK) return s;
+    s = tof_tensor(ctx, (double *)oct.p, stream);
+    hipError_t e = hipSuccess;
+    if (s == TOF_OK) {
+        e = launch_tensor_full(st, (const double *)oct.p, ctx->nx, ctx->ny, ctx->nz, N);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(oct.p);
+    if (s != TOF_OK) return s;
+    if (e != hipSuccess) return hip_fail(ctx, e, "tof_tensor_full");
+    return TOF_OK;
+}
+
 tof_status tof_profile_enable(tof_ctx *ctx, int32_t enable)
 {
     if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
     if (enable && ctx->prof_ev.empty()) {
-        ctx->prof_ev.resize((size_t)TOF_PROFILE_SLOTS * kProfCalls * 2, nullptr);
-        for (hipEvent_t &ev : ctx->prof_ev) HIP_TRY(ctx, hipEventCreate(&ev));
+        const size_t n = (size_t)TOF_PROFILE_SLOTS * kProfCalls;
+        ctx->prof_ev.resize(n, nullptr);
+        ctx->prof_refs.resize(kProfAnchors, nullptr);
+        ctx->prof_rec_ref.assign(n, -1);
+        ctx->prof_rec_prev.assign(n, nullptr);
+        // timing events without the system-scope fence: the default event
+        // writes back the L2 at each record, which lengthens the timed launch
+        for (hipEvent_t &ev : ctx->prof_ev) HIP_TRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+        for (hipEvent_t &ev : ctx->prof_refs) HIP_TRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+        for (auto &pair : ctx->prof_burst_ev)
+            for (hipEvent_t &ev : pair) HIP_TRY(ctx, hipEventCreate(&ev));
     }
     ctx->prof_on = enable != 0;
+    ctx->prof_last = nullptr;   // a chain of timed launches starts afresh
     return TOF_OK;
 }
 
@@ -1113,18 +1212,62 @@ tof_status tof_profile_read(tof_ctx *ctx, double ms_host[], int64_t count_host[]
 {
     if (!ctx || !ms_host || !count_host || !bytes_host) return fail(ctx, TOF_ERR_INVALID, "null argument");
     for (int slot = 0; slot < TOF_PROFILE_SLOTS; ++slot) {
-        double sum = 0.0;
+        // launches timed from the end of the one before them, and the first
+        // launches of chains (from their anchor) apart: a slot reports the
+        // former when it has any
+        double sum_c = 0.0, sum_a = 0.0;
+        int64_t n_c = 0, n_a = 0;
         for (int i = 0; i < ctx->prof_calls[slot]; ++i) {
-            hipEvent_t *ev = &ctx->prof_ev[((size_t)slot * kProfCalls + i) * 2];
-            HIP_TRY(ctx, hipEventSynchronize(ev[1]));
-            float ms = 0.f;
-            HIP_TRY(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]));
-            sum += ms;
+            const size_t idx = (size_t)slot * kProfCalls + i;
+            hipEvent_t stop = ctx->prof_ev[idx], ref = ctx->prof_refs[(size_t)ctx->prof_rec_ref[idx]];
+            HIP_TRY(ctx, hipEventSynchronize(stop));
+            float a = 0.f;
+            HIP_TRY(ctx, hipEventElapsedTime(&a, ref, stop));
+            if (hipEvent_t prev = ctx->prof_rec_prev[idx]) {
+                float b = 0.f;
+                HIP_TRY(ctx, hipEventElapsedTime(&b, ref, prev));
+                sum_c += (double)a - (double)b;
+                ++n_c;
+            } else {
+                sum_a += a;
+                ++n_a;
+            }
         }
-        ms_host[slot] = sum;
-        count_host[slot] = ctx->prof_calls[slot];
+        ms_host[slot] = n_c ? sum_c : sum_a;
+        count_host[slot] = n_c ? n_c : n_a;
         bytes_host[slot] = ctx->prof_bytes[slot];
         ctx->prof_calls[slot] = 0;
+    }
+    ctx->prof_nref = 0;
+    ctx->prof_last = nullptr;
+    return TOF_OK;
+}
+
+tof_status tof_profile_burst(tof_ctx *ctx, uint32_t slot_mask, int32_t repeats)
+{
+    if (!ctx) return fail(nullptr, TOF_ERR_INVALID, "null context");
+    if (!ctx->prof_on) return fail(ctx, TOF_ERR_INVALID, "timing is off (tof_profile_enable first)");
+    if (repeats < 1 || repeats > TOF_PROFILE_MAX_BURST)
+        return fail(ctx, TOF_ERR_INVALID, "repeats outside [1, " + std::to_string(TOF_PROFILE_MAX_BURST) + "]");
+    if (slot_mask >> TOF_PROFILE_SLOTS) return fail(ctx, TOF_ERR_INVALID, "slot_mask names no slot");
+    ctx->prof_burst_mask = slot_mask;
+    ctx->prof_burst_reps = repeats;
+    for (int slot = 0; slot < TOF_PROFILE_SLOTS; ++slot)
+        if ((slot_mask >> slot) & 1u) ctx->prof_burst_done[slot] = 0;
+    return TOF_OK;
+}
+
+tof_status tof_profile_burst_read(tof_ctx *ctx, double ms_host[])
+{
+    if (!ctx || !ms_host) return fail(ctx, TOF_ERR_INVALID, "null argument");
+    for (int slot = 0; slot < TOF_PROFILE_SLOTS; ++slot) {
+        ms_host[slot] = 0.0;
+        if (!ctx->prof_burst_done[slot]) continue;
+        HIP_TRY(ctx, hipEventSynchronize(ctx->prof_burst_ev[slot][1]));
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->prof_burst_ev[slot][0], ctx->prof_burst_ev[slot][1]));
+        ms_host[slot] = (double)ms / ctx->prof_burst_done[slot];
+        ctx->prof_burst_done[slot] = 0;
     }
     return TOF_OK;
 }

@@ -2,6 +2,7 @@
 // kernels (kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -175,7 +176,14 @@ inline void batch_record(const void *kernel, dim3 grid, dim3 block, A a)
 // items (grid times block), for the per-launch timing record; set by TOF_LAUNCH.
 extern thread_local const char *g_last_kernel;
 extern thread_local long long g_last_items;
-#define TOF_LAUNCH(K, G, B, ...)                                                                  \
+// While set, the next TOF_LAUNCH takes this event as its kernel's own
+// completion timestamp (hipExtLaunchKernelGGL: no packet is added to the
+// stream) and clears it; g_prof_launches counts the launches meanwhile and
+// g_launch_seq all launches.
+extern thread_local hipEvent_t g_prof_stop;
+extern thread_local int g_prof_launches;
+extern thread_local unsigned long long g_launch_seq;
+#define TOF_LAUNCH(K, G, B, SHM, ST, ...)                                                         \
     do {                                                                                          \
         g_last_kernel = #K;                                                                       \
         const dim3 g_ = dim3(G), b_ = dim3(B);                                                    \
@@ -184,7 +192,14 @@ extern thread_local long long g_last_items;
             g_batch_unbatchable = #K;                                                             \
             break;                                                                                \
         }                                                                                         \
-        hipLaunchKernelGGL(K, g_, b_, __VA_ARGS__);                                               \
+        ++g_prof_launches;                                                                        \
+        ++g_launch_seq;                                                                           \
+        if (g_prof_stop) {                                                                        \
+            hipExtLaunchKernelGGL(K, g_, b_, SHM, ST, nullptr, g_prof_stop, 0, __VA_ARGS__);      \
+            g_prof_stop = nullptr;                                                                \
+        } else {                                                                                  \
+            hipLaunchKernelGGL(K, g_, b_, SHM, ST, __VA_ARGS__);                                  \
+        }                                                                                         \
     } while (0)
 
 // Launch of a batchable kernel K with the kernel arguments that follow A
@@ -332,6 +347,8 @@ hipError_t launch_trace_accumulate(hipStream_t st, const double *wrapped, int Lx
                                    double *T);
 hipError_t launch_trace_error(hipStream_t st, const double *T, long long n, unsigned long long *maxbits);
 hipError_t launch_add_at(hipStream_t st, double *a, long long idx, double v);
+// out [6][2nz-1][2ny-1][2nx-1]: the tensor at every signed offset from the octant [6][nz][ny][nx]
+hipError_t launch_tensor_full(hipStream_t st, const double *oct, int nx, int ny, int nz, double *out);
 
 hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, double dx,
                                  double dy, double dz, double *lat /* [lz][ly][lx][2] */);

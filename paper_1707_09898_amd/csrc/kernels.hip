@@ -939,6 +939,26 @@ __global__ __launch_bounds__(kThreads) void k_trace_error(const double *T, long 
     if ((threadIdx.x & 63) == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
 }
 
+// The tensor at every signed offset from its octant: out[c][kz + nz - 1]
+// [ky + ny - 1][kx + nx - 1] = N_c(|kx|, |ky|, |kz|) times the component's
+// parity signs (xy odd in x and y, xz in x and z, yz in y and z).
+__global__ __launch_bounds__(kThreads) void k_tensor_full(const double *oct, int nx, int ny, int nz, double *out)
+{
+    const int fx = 2 * nx - 1, fy = 2 * ny - 1, fz = 2 * nz - 1;
+    const long long per = (long long)fx * fy * fz, octn = (long long)nx * ny * nz;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < 6 * per;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(q / per);
+        const long long r = q - c * per;
+        const int kx = (int)(r % fx) - (nx - 1);
+        const int ky = (int)((r / fx) % fy) - (ny - 1);
+        const int kz = (int)(r / ((long long)fx * fy)) - (nz - 1);
+        double v = oct[c * octn + ((long long)abs(kz) * ny + abs(ky)) * nx + abs(kx)];
+        if ((comp_odd_x(c) && kx < 0) != (comp_odd_y(c) && ky < 0) != (comp_odd_z(c) && kz < 0)) v = -v;
+        out[q] = v;
+    }
+}
+
 // One value added to one element (the test hook that perturbs the tensor).
 __global__ void k_add_at(double *a, long long idx, double v)
 {
@@ -1825,6 +1845,15 @@ hipError_t launch_trace_error(hipStream_t st, const double *T, long long n, unsi
     long long blocks = (n + kThreads - 1) / kThreads;
     blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
     TOF_LAUNCH(k_trace_error, dim3((int)blocks), dim3(kThreads), 0, st, T, n, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_tensor_full(hipStream_t st, const double *oct, int nx, int ny, int nz, double *out)
+{
+    const long long n = 6LL * (2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1);
+    long long blocks = (n + kThreads - 1) / kThreads;
+    blocks = blocks > 65536 ? 65536 : blocks;
+    TOF_LAUNCH(k_tensor_full, dim3((int)blocks), dim3(kThreads), 0, st, oct, nx, ny, nz, out);
     return hipGetLastError();
 }
 

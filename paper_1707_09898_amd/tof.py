@@ -22,9 +22,10 @@ STATUS = {0: "TOF_OK", -1: "TOF_ERR_INVALID", -2: "TOF_ERR_UNSUPPORTED", -3: "TO
 
 EXPORTS = ["tof_create", "tof_destroy", "tof_set_design", "tof_set_objective", "tof_field",
            "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_project_step_static", "tof_tensor",
+           "tof_tensor_full",
            "tof_padded_lengths", "tof_workspace_bytes", "tof_ctx_bytes", "tof_last_error", "tof_dd_newell_host",
-           "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_set_option",
-           "tof_batch_create", "tof_batch_run", "tof_batch_launches", "tof_batch_destroy"]
+           "tof_profile_enable", "tof_profile_read", "tof_profile_kernel", "tof_profile_burst",
+           "tof_profile_burst_read", "tof_set_option", "tof_batch_create", "tof_batch_run", "tof_batch_launches", "tof_batch_destroy"]
 
 OPT_ZSUM, OPT_FUSE_YZ, OPT_FUSE_OBJECTIVE = 1, 2, 3
 OPT_X_TILE, OPT_GATHER_GROUPS, OPT_SCATTER_GROUPS = 4, 5, 6
@@ -82,6 +83,7 @@ def lib():
         L.tof_project_step.argtypes = [vp, vp, vp, dbl, vp]
         L.tof_project_step_static.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(BoxC), vp, vp, vp, dbl, vp]
         L.tof_tensor.argtypes = [vp, vp, vp]
+        L.tof_tensor_full.argtypes = [vp, vp, vp]
         L.tof_padded_lengths.argtypes = [vp, ctypes.POINTER(i32)]
         L.tof_workspace_bytes.argtypes = [ctypes.POINTER(Grid)]
         L.tof_workspace_bytes.restype = ctypes.c_size_t
@@ -95,6 +97,8 @@ def lib():
         L.tof_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(dbl)]
         L.tof_profile_kernel.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
         L.tof_profile_kernel.restype = ctypes.c_char_p
+        L.tof_profile_burst.argtypes = [vp, ctypes.c_uint32, i32]
+        L.tof_profile_burst_read.argtypes = [vp, ctypes.POINTER(dbl)]
         L.tof_set_option.argtypes = [vp, i32, i32]
         L.tof_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                        i32, ctypes.POINTER(vp)]
@@ -105,8 +109,8 @@ def lib():
         L.tof_batch_destroy.restype = None
         for name in ("tof_create", "tof_set_design", "tof_set_objective", "tof_field",
                      "tof_objective_and_grad", "tof_adjoint", "tof_project_step", "tof_project_step_static",
-                     "tof_tensor", "tof_padded_lengths", "tof_profile_enable", "tof_profile_read", "tof_set_option",
-                     "tof_batch_create", "tof_batch_run"):
+                     "tof_tensor", "tof_tensor_full", "tof_padded_lengths", "tof_profile_enable", "tof_profile_read",
+                     "tof_profile_burst", "tof_profile_burst_read", "tof_set_option", "tof_batch_create", "tof_batch_run"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,6 +234,13 @@ class Engine:
         self._check(lib().tof_tensor(self._ctx, ctypes.c_void_p(N.data_ptr()), _stream_ptr(stream)))
         return N
 
+    def tensor_full(self, stream=None):
+        """The tensor at every signed offset, [6][2nz-1][2ny-1][2nx-1] (tof_tensor_full)."""
+        nx, ny, nz = self.n
+        N = self.torch.empty((6, 2 * nz - 1, 2 * ny - 1, 2 * nx - 1), dtype=self.torch.float64, device="cuda")
+        self._check(lib().tof_tensor_full(self._ctx, ctypes.c_void_p(N.data_ptr()), _stream_ptr(stream)))
+        return N
+
     def profile(self, enable: bool = True):
         self._check(lib().tof_profile_enable(self._ctx, 1 if enable else 0))
 
@@ -240,6 +251,20 @@ class Engine:
         by = (ctypes.c_double * PROFILE_SLOTS)()
         self._check(lib().tof_profile_read(self._ctx, ms, cnt, by))
         return [(PROFILE_NAMES[i], ms[i], cnt[i], by[i]) for i in range(PROFILE_SLOTS)]
+
+    def profile_burst(self, slots, repeats: int):
+        """Arm a burst of `repeats` extra back-to-back launches for every slot
+        in `slots` (indices) at the next call (tof_profile_burst)."""
+        mask = 0
+        for i in slots:
+            mask |= 1 << int(i)
+        self._check(lib().tof_profile_burst(self._ctx, mask, int(repeats)))
+
+    def profile_burst_read(self):
+        """Per slot: mean ms per launch of its last burst, 0.0 where none ran."""
+        ms = (ctypes.c_double * PROFILE_SLOTS)()
+        self._check(lib().tof_profile_burst_read(self._ctx, ms))
+        return [ms[i] for i in range(PROFILE_SLOTS)]
 
     def profile_kernels(self, with_items: bool = False):
         """Per slot: the name of the kernel last timed there ("" if none), or

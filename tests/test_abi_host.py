@@ -63,6 +63,9 @@ def test_null_context_calls_fail_cleanly():
     assert L.tof_adjoint(None, None, None, None, None) == -1
     assert L.tof_project_step(None, None, None, 0.1, None) == -1
     assert L.tof_tensor(None, None, None) == -1
+    assert L.tof_tensor_full(None, None, None) == -1
+    assert L.tof_profile_burst(None, 1, 10) == -1
+    assert L.tof_profile_burst_read(None, None) == -1
     assert L.tof_workspace_bytes(None) == 0
     assert L.tof_ctx_bytes(None) == 0
     assert L.tof_set_option(None, tof.OPT_FUSE_YZ, 1) == -1

@@ -105,6 +105,28 @@ def masked(w, seed, fraction=0.6):
     return dataclasses.replace(w, mask=wl.random_mask(seed, w.n, fraction))
 
 
+def test_gpu_tensor_full_matches_oracle_at_signed_offsets(torch):
+    """tof_tensor_full: every signed offset, against the oracle's octant with
+    the parity signs (oracle.tensor_at), and the symmetry N(-k) = N(k)."""
+    n, h = (7, 6, 5), (1.0, 0.8, 1.3)
+    e = tof().Engine(n, h, "f64")
+    F = host(e.tensor_full())
+    assert F.shape == (6, 9, 11, 13)
+    table = oracle.newell_table(n, h)
+    comps = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    scale = np.abs(table).max()
+    for kz in range(-4, 5):
+        for ky in range(-5, 6):
+            for kx in range(-6, 7):
+                ref = oracle.tensor_at(table, (kx, ky, kz))
+                got = F[:, kz + 4, ky + 5, kx + 6]
+                for c, (a, b) in enumerate(comps):
+                    assert abs(got[c] - ref[a, b]) <= 1e-15 * scale, (c, kx, ky, kz)
+    # N(-k) = N(k); exact but for the rounding noise of the odd components on
+    # their zero planes (k_a = 0), whose sign the parity flips
+    assert np.abs(F - F[:, ::-1, ::-1, ::-1]).max() <= 2e-15 * scale
+
+
 # ---------------------------------------------------------------- field
 FIELD_CASES = [
     ("c1", lambda: wl.config1()),
@@ -499,3 +521,60 @@ def test_gpu_graph_replays_of_one_evaluation(torch):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(g, g_ref) and torch.equal(J, J_ref), k
+
+
+def test_gpu_profile_launch_times_add_up_to_the_step(torch):
+    """Per-launch timing over consecutive evaluations: with an event per
+    launch, every launch after the first is timed from the end of the one
+    before it, so the slots' means add up to one evaluation as it runs with
+    those events (each launch a little longer: between 0.9 and 1.3 times
+    the plain step) and every slot of the fused path counts one launch per
+    evaluation (the chain's first launch aside).  Bursts (each pass again
+    back to back, events around the burst only) add up to the plain step
+    within 15%, and leave the evaluation's results bit for bit unchanged."""
+    w = wl.config3()
+    e = tof().engine_for(w, "f32")
+    rho = torch.as_tensor(w.rho, dtype=e.dtype, device="cuda")
+    grad = torch.empty_like(rho)
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    for _ in range(20):
+        e.objective_and_grad(rho, grad, J)
+    n = 100
+
+    def step_ms():
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(n):
+            e.objective_and_grad(rho, grad, J)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / n
+
+    step = sorted(step_ms() for _ in range(3))[1]
+    g0, J0 = grad.clone(), J.clone()
+    e.profile(True)
+    for _ in range(n):
+        e.objective_and_grad(rho, grad, J)
+    prof = e.profile_read()
+    used = [(i, name, ms, cnt) for i, (name, ms, cnt, _) in enumerate(prof) if cnt > 0]
+    bursts = []
+    for _ in range(3):
+        e.profile_burst([i for (i, _, _, _) in used], 50)
+        grad.fill_(float("nan"))
+        e.objective_and_grad(rho, grad, J)
+        bursts.append(e.profile_burst_read())
+        assert torch.equal(grad, g0) and torch.equal(J, J0)
+    e.profile_read()
+    e.profile(False)
+    burst = [sorted(b[i] for b in bursts)[1] for i in range(len(bursts[0]))]
+    say("step", step, "event per launch", [(name, round(ms / cnt * 1e3, 2), cnt) for (_, name, ms, cnt) in used],
+        "bursts", [(name, round(burst[i] * 1e3, 2)) for (i, name, _, _) in used])
+    assert len(used) == 5
+    assert sorted(cnt for (_, _, _, cnt) in used) == [n - 1, n, n, n, n]
+    total = sum(ms / cnt for (_, _, ms, cnt) in used)
+    assert 0.9 * step <= total <= 1.3 * step, (total, step)
+    assert all(burst[i] > 0 for (i, _, _, _) in used)
+    btotal = sum(burst[i] for (i, _, _, _) in used)
+    assert 0.9 * step <= btotal <= 1.15 * step, (btotal, step)
+    e.close()
