@@ -319,8 +319,12 @@ def main():
         ms = median(loops)
         J_main = float(J.item())
         grad_main = grad.double()   # the timed path's gradient, for the precision report
+        # bursts for the FP32 value only: FP64 arrays are twice the size, and
+        # a pass repeated on its own finds more of its inputs in the chip's
+        # last-level cache than it does inside the evaluation
         prof, kernels, burst_ms = slot_times(tof, e, lambda: e.objective_and_grad(rho, grad, J),
-                                             args.profile_steps, args.burst_launches, args.bursts)
+                                             args.profile_steps, args.burst_launches if dtype == "f32" else 0,
+                                             args.bursts)
         paths = {}
         if dtype == "f32" and not args.no_paths:
             # the same evaluation on the other pass choices (direct z sum unfused; FFTs along z)
