@@ -141,6 +141,33 @@ def slot_times(tof, e, call, steps, burst_launches, bursts):
     return prof, kernels, burst_ms
 
 
+def stream_reference(torch, mib=1024, loops=10):
+    """What plain streaming kernels reach on this GPU, per read : write mix
+    (torch's elementwise kernels over arrays of `mib` MiB of FP32; bytes =
+    what each must read and write; median of 3 timed loops): the practical
+    ceiling the passes' own read : write mixes can be set against."""
+    n = mib * 2 ** 20 // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    c = torch.empty(n, dtype=torch.complex64, device="cuda")
+    c.copy_(x)
+    cases = {
+        "write only (fill)": (lambda: y.fill_(0.5), 4 * n),
+        "read 1 : write 2 (real to complex)": (lambda: c.copy_(x), 12 * n),
+        "read 1 : write 1 (copy)": (lambda: y.copy_(x), 8 * n),
+        "read 2 : write 1 (complex to real part)": (lambda: y.copy_(c.real), 12 * n),
+        "read only (sum)": (lambda: x.sum(), 4 * n),
+    }
+    out = {}
+    for name, (fn, by) in cases.items():
+        for _ in range(3):
+            fn()
+        ms = median(timed_loops(torch, fn, loops, 3))
+        out[name] = round(by / (ms * 1e-3) / 1e9, 1)
+    del x, y, c
+    return out
+
+
 def full_field_measurement(torch, tof, w, steps, repeats, burst_launches=100, bursts=5):
     """The five-pass FFT pipeline at 256 x 256 x 128 FP32: (a) the field H_z
     of the whole grid (tof_field, FFTs along x, y and z with the tensor
@@ -276,6 +303,8 @@ def main():
                     help="launches per burst of each pass for the per-kernel times (0: an event per launch)")
     ap.add_argument("--bursts", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch measurement")
+    ap.add_argument("--no-stream-reference", action="store_true",
+                    help="skip the plain streaming kernels (practical bandwidth per read : write mix)")
     ap.add_argument("--no-paths", action="store_true", help="skip timing the unfused pass choices")
     ap.add_argument("--batch-replays", type=int, default=20)
     ap.add_argument("--batch-streams", type=int, default=4)
@@ -439,6 +468,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "bytes_per_launch": dom[3], "avg_launch_us": dom[1] * 1e3},
     }
+    if not args.no_stream_reference:
+        out["stream_reference_GBps"] = stream_reference(torch)
+        print(f"[bench] streaming reference (GB/s): {out['stream_reference_GBps']}", file=sys.stderr, flush=True)
     if not args.no_full_field:
         out["full_field_pipeline"] = full_field_measurement(torch, tof, w, max(10, args.steps // 2), args.repeats,
                                                             args.burst_launches, args.bursts)

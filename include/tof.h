@@ -346,7 +346,7 @@ const char *tof_profile_kernel(const tof_ctx *ctx, int32_t slot, int64_t *work_i
  *                   row pair a block.
  *   TOF_OPT_GATHER_GROUPS, TOF_OPT_SCATTER_GROUPS  row groups of the fused
  *                   y / z-sum kernels (blocks = groups x (Lx/2+1)), 1 to
- *                   64, or 0 for the default (6 and 8, at most the rows).
+ *                   64, or 0 for the default (3 and 8, at most the rows).
  *                   The gather's groups are added in group order, so its
  *                   group count changes the rounding of the sum.
  */

@@ -160,10 +160,11 @@ constexpr int kProfAnchors = 256;
 // each within half an ulp of |N| <= 1 after the double-double evaluation)
 constexpr double kTraceTol = 1e-12;
 // Row groups of the fused y / z-sum kernels (blocks = groups x (Lx/2+1)).
-// At 256x256x128 the gather (whose groups the objective kernel adds) runs
-// best with 6 among 4 to 8, the scatter with 8 among 4, 8 and 16.
+// At 256x256x128 the evaluation runs best with 3 gather groups among 2 to 6
+// (6 makes the gather no faster and the objective kernel, which adds the
+// groups' copies, 0.9 us slower), the scatter with 8 among 4, 6, 8 and 16.
 #ifndef TOF_YZ_GATHER_GROUPS
-#define TOF_YZ_GATHER_GROUPS 6
+#define TOF_YZ_GATHER_GROUPS 3
 #endif
 #ifndef TOF_YZ_SCATTER_GROUPS
 #define TOF_YZ_SCATTER_GROUPS 8
