@@ -1312,9 +1312,11 @@ __global__ __launch_bounds__(kThreads) void k_extract_kt(const cplx<double> *B, 
 // -- pass 1: real-to-complex FFT along x, transposed store ------------------
 // Block: NLC complex lines = 2 NLC source rows of one z (and one component);
 // each thread transforms LPT of them in turn.  HALF (design sources only):
-// the design rows fill exactly the lower half of the line (x in [0, L/2)),
-// so the upper half is neither loaded nor transformed in the first stage.
-template <typename R, int L, int E, int NLC, int LPT, bool HALF>
+// 1: the design rows lie in the lower half of the line (x < L/2, which the
+// 2n padding always gives), 2: they fill it exactly; either way the upper
+// half is neither loaded nor transformed in the first stage, and with 2 the
+// loads need no clamp and no range select.
+template <typename R, int L, int E, int NLC, int LPT, int HALF>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg(int mode, DesignDev<R> dsg, View4<const R> src,
                                                                 Box S, cplx<R> *out, int hx, const cplx<R> *table)
 {
@@ -1333,7 +1335,7 @@ __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_
 #undef TOF_BGZ
 }
 
-template <typename R, int L, int E, int NLC, int LPT, bool HALF>
+template <typename R, int L, int E, int NLC, int LPT, int HALF>
 __global__ __launch_bounds__((NLC / LPT) * (L / E)) __attribute__((amdgpu_waves_per_eu(TOF_XF_WAVES))) void k_xf_reg_batch(
     const XfArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
@@ -1480,7 +1482,7 @@ hipError_t allow_lds(K kernel, size_t bytes)
 #define TOF_XI_LPT512_F64 TOF_XI_LPT512
 #endif
 
-template <typename R, int L, int NLC, int LPT, bool HALF>
+template <typename R, int L, int NLC, int LPT, int HALF>
 hipError_t launch_xf_reg_h(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
                            const FftPlanDev &plan, cplx<R> *out, int hx, int xtile)
 {
@@ -1501,16 +1503,20 @@ hipError_t launch_xf_reg_h(hipStream_t st, int mode, const DesignDev<R> &dsg, Vi
     return hipGetLastError();
 }
 
-// Design sources whose rows fill exactly x in [0, L/2) take the HALF form.
+// Design sources take the HALF forms: 2 when their rows fill exactly x in
+// [0, L/2), else 1 when the grid's rows lie in the lower half (always, with
+// L >= 2 nx).
 template <typename R, int L, int NLC, int LPT>
 hipError_t launch_xf_reg(hipStream_t st, int mode, const DesignDev<R> &dsg, View4<const R> src, Box S, int c_in,
                          const FftPlanDev &plan, cplx<R> *out, int hx, int xtile)
 {
     const int xl = S.x0 > dsg.design.x0 ? S.x0 : dsg.design.x0;
     const int xh = S.x1 < dsg.design.x1 ? S.x1 : dsg.design.x1;
-    const bool half = mode != SRC_ARRAY && xl == 0 && xh == L / 2 && dsg.nx == L / 2;
-    if (half) return launch_xf_reg_h<R, L, NLC, LPT, true>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
-    return launch_xf_reg_h<R, L, NLC, LPT, false>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    if (mode != SRC_ARRAY && xl == 0 && xh == L / 2 && dsg.nx == L / 2)
+        return launch_xf_reg_h<R, L, NLC, LPT, 2>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    if (mode != SRC_ARRAY && dsg.nx <= L / 2)
+        return launch_xf_reg_h<R, L, NLC, LPT, 1>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
+    return launch_xf_reg_h<R, L, NLC, LPT, 0>(st, mode, dsg, src, S, c_in, plan, out, hx, xtile);
 }
 
 template <typename R>

@@ -131,10 +131,11 @@ struct YzKArgs {
 // A is [CI][hx][nzs][nys] (the x pass output); part is [G][CO][hx][nzt][nyt]
 // with y from yt0: G copies of the inverse x pass's input, to be added; with
 // kxf [G][CO][nzt][nyt][hx] (rows with kx fastest, for the fused objective).
-// HALF: the source rows fill exactly the lower half of the line (ys0 = 0,
-// nys = L/2), so the loads need no bounds and the first stage skips the
-// zero half.
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+// HALF: 1: the source rows lie in the lower half of the line (ys0 + nys <=
+// L/2, which the 2n padding always gives), so only that half is loaded and
+// the first stage skips the zero half; 2: they fill it exactly (ys0 = 0,
+// nys = L/2), so the loads need no bounds either.
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 #undef TOF_BGZ
 }
 
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
     BlockPos bp;
@@ -280,7 +281,7 @@ YzKArgs<R> scatter_args(const YzSumArgs<R> &a, const KtDev<R> &kt, const Product
                       table, 0, a.jf};
 }
 
-template <typename R, int L, int CI, int CO, int NC, int PAR, bool HALF>
+template <typename R, int L, int CI, int CO, int NC, int PAR, int HALF>
 hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
                           const ProductDev &prod, const cplx<R> *table, bool check_only)
 {
@@ -313,8 +314,8 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     if (a.nzs == 1) {
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), st,
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>), grid, dim3(kBlock), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -322,8 +323,8 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     } else if (a.nzs <= NRM) {
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), st,
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>), grid, dim3(kBlock), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -332,16 +333,20 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     return hipErrorInvalidValue;
 }
 
-// The many-row side fills exactly the lower half of the y line: the source
-// rows for the gather, the target rows for the scatter.
+// Where the many-row side lies in the y line: 2 when it fills exactly the
+// lower half (the source rows for the gather, the target rows for the
+// scatter), 1 when the gather's source rows lie in the lower half, else 0
+// (the scatter has forms 2 and 0 only).
 template <typename R, int L, int CI, int CO, int NC, int PAR>
 hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
                           const ProductDev &prod, const cplx<R> *table, bool check_only)
 {
     const bool gather = a.nzt <= kZsumMaxRows;
-    const bool half = gather ? (a.ys0 == 0 && a.nys == L / 2) : (a.yt0 == 0 && a.nyt == L / 2);
-    if (half) return launch_yzsum_h<R, L, CI, CO, NC, PAR, true>(st, a, rows, kt, prod, table, check_only);
-    return launch_yzsum_h<R, L, CI, CO, NC, PAR, false>(st, a, rows, kt, prod, table, check_only);
+    const int half = gather ? (a.ys0 == 0 && a.nys == L / 2 ? 2 : (a.ys0 + a.nys <= L / 2 ? 1 : 0))
+                            : (a.yt0 == 0 && a.nyt == L / 2 ? 2 : 0);
+    if (half == 2) return launch_yzsum_h<R, L, CI, CO, NC, PAR, 2>(st, a, rows, kt, prod, table, check_only);
+    if (half == 1) return launch_yzsum_h<R, L, CI, CO, NC, PAR, 1>(st, a, rows, kt, prod, table, check_only);
+    return launch_yzsum_h<R, L, CI, CO, NC, PAR, 0>(st, a, rows, kt, prod, table, check_only);
 }
 
 template <typename R, int L>
