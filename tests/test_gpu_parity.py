@@ -190,6 +190,12 @@ GRAD_CASES = [
     ("masked_gradxy", lambda: masked(wl.small_random(44, n=(16, 16, 11), design=(0, 16, 0, 16, 0, 7)), 44)),
     ("masked_vector", lambda: masked(wl.small_random(45, n=(10, 12, 9), j_kind=wl.J_MEAN_SQ_H_TARGET,
                                                      varying_m0=True), 45, 0.5)),
+    # Lx = Ly = 32 for 13 x 11 cells: rows in the lower half of the padded
+    # lines without filling it (the forward x pass's and the gather's bounded
+    # lower-half forms), with the design box at the origin and offset in x and y
+    ("lower_half_rows", lambda: dataclasses.replace(wl.small_random(46, n=(13, 11, 10)), pad=(32, 32, 20))),
+    ("lower_half_offset_design", lambda: dataclasses.replace(
+        wl.small_random(47, n=(13, 11, 10), design=(2, 12, 3, 10, 0, 6)), pad=(32, 32, 20))),
 ]
 
 
