@@ -11,9 +11,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtof.so")
 
-SOURCES = ["kernels.hip", "yzsum.hip", "api.cpp"]
-HEADERS = ["dd.h", "fft.h", "fft_reg.h", "engine.h", "device_common.h", "body_xf_reg.inc", "body_xi_reg.inc",
-           "body_objective_xf.inc", "body_yzsum_gather.inc", "body_yzsum_scatter.inc"]
+# kernels.hip and yzsum.hip are compiled once per precision (the *_f32 and
+# *_f64 units include them), so that the halves build in parallel
+SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "yzsum_f32.hip", "yzsum_f64.hip", "api.cpp"]
+HEADERS = ["kernels.hip", "yzsum.hip", "dd.h", "fft.h", "fft_reg.h", "engine.h", "device_common.h",
+           "body_xf_reg.inc", "body_xi_reg.inc", "body_objective_xf.inc", "body_yzsum_gather.inc",
+           "body_yzsum_scatter.inc"]
 
 # Packed FP32 instructions are kept out of every kernel (compiler option).
 HIPCC_FLAGS = [

@@ -1759,12 +1759,14 @@ hipError_t launch_x_inverse(hipStream_t st, const cplx<R> *C, int hx, int c, Box
     return hipGetLastError();
 }
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_finalize_j(hipStream_t st, const JFinal &jf)
 {
     if (!jf.partials || !jf.J || jf.nb < 1) return hipErrorInvalidValue;
     TOF_LAUNCH(k_finalize_j, dim3(1), dim3(64), 0, st, jf);
     return hipGetLastError();
 }
+#endif
 
 template <typename R>
 hipError_t launch_objective_xf(hipStream_t st, const ObjectiveDev<R> &o, const FftPlanDev &plan, cplx<R> *A, int hx,
@@ -1836,6 +1838,7 @@ hipError_t launch_nonfinite(hipStream_t st, const R *a, long long n, unsigned lo
     return hipGetLastError();
 }
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_trace_accumulate(hipStream_t st, const double *wrapped, int Lx, int Ly, int nx, int ny, int nz,
                                    double *T)
 {
@@ -1844,7 +1847,9 @@ hipError_t launch_trace_accumulate(hipStream_t st, const double *wrapped, int Lx
     TOF_LAUNCH(k_trace_accumulate, dim3((int)blocks), dim3(kThreads), 0, st, wrapped, Lx, Ly, nx, ny, nz, T);
     return hipGetLastError();
 }
+#endif
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_trace_error(hipStream_t st, const double *T, long long n, unsigned long long *maxbits)
 {
     TOF_LAUNCH(k_clear_u64, dim3(1), dim3(64), 0, st, maxbits, 1);
@@ -1853,7 +1858,9 @@ hipError_t launch_trace_error(hipStream_t st, const double *T, long long n, unsi
     TOF_LAUNCH(k_trace_error, dim3((int)blocks), dim3(kThreads), 0, st, T, n, maxbits);
     return hipGetLastError();
 }
+#endif
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_tensor_full(hipStream_t st, const double *oct, int nx, int ny, int nz, double *out)
 {
     const long long n = 6LL * (2 * nx - 1) * (2 * ny - 1) * (2 * nz - 1);
@@ -1862,13 +1869,17 @@ hipError_t launch_tensor_full(hipStream_t st, const double *oct, int nx, int ny,
     TOF_LAUNCH(k_tensor_full, dim3((int)blocks), dim3(kThreads), 0, st, oct, nx, ny, nz, out);
     return hipGetLastError();
 }
+#endif
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_add_at(hipStream_t st, double *a, long long idx, double v)
 {
     TOF_LAUNCH(k_add_at, dim3(1), dim3(64), 0, st, a, idx, v);
     return hipGetLastError();
 }
+#endif
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, double dx, double dy,
                                  double dz, double *lat)
 {
@@ -1878,7 +1889,9 @@ hipError_t launch_newell_lattice(hipStream_t st, int c, int lx, int ly, int lz, 
     TOF_LAUNCH(k_newell_lattice, dim3(blocks), dim3(128), 0, st, c, lx, ly, lz, dx, dy, dz, lat);
     return hipGetLastError();
 }
+#endif
 
+#ifndef TOF_NO_COMMON
 hipError_t launch_newell_stencil(hipStream_t st, int c, int mx, int my, int mz, int lx, int ly, double dx,
                                  double dy, double dz, const double *lat, double *wrapped, int Lx, int Ly,
                                  int Lz, double *octant)
@@ -1891,6 +1904,7 @@ hipError_t launch_newell_stencil(hipStream_t st, int c, int mx, int my, int mz, 
                        wrapped, Lx, Ly, Lz, octant);
     return hipGetLastError();
 }
+#endif
 
 template <typename R>
 hipError_t launch_extract_spectrum(hipStream_t st, const cplx<double> *B, int hx, int Ly, int Lz,
@@ -1993,5 +2007,9 @@ hipError_t launch_extract_kt(hipStream_t st, const cplx<double> *B, int hx, int 
                                                    double, R *, int, int, unsigned long long *,          \
                                                    unsigned long long *);
 
+#ifndef TOF_NO_F32
 TOF_INSTANTIATE(float)
+#endif
+#ifndef TOF_NO_F64
 TOF_INSTANTIATE(double)
+#endif

@@ -387,7 +387,11 @@ hipError_t launch_yz_sum(hipStream_t st, const YzSumArgs<R> &a, const KtDev<R> &
     }
 }
 
+#ifndef TOF_NO_F32
 template hipError_t launch_yz_sum<float>(hipStream_t, const YzSumArgs<float> &, const KtDev<float> &,
                                          const ProductDev &, const FftPlanDev &, bool);
+#endif
+#ifndef TOF_NO_F64
 template hipError_t launch_yz_sum<double>(hipStream_t, const YzSumArgs<double> &, const KtDev<double> &,
                                           const ProductDev &, const FftPlanDev &, bool);
+#endif
