@@ -51,7 +51,11 @@ using namespace tofdev;
 #endif
 
 constexpr int kE = 8;           // elements per thread of a y line
-constexpr int kBlock = 256;     // threads per block
+// Threads per block: 256 for lines of 256 and 512 (8 or 4 lines side by
+// side), one wave for shorter lines (4 lines of 128, 8 of 64, 16 of 32):
+// short lines come with few rows a block, and the gather's line slots are
+// added by one slot at the end.
+constexpr int yz_block(int L) { return L >= 256 ? 256 : 64; }
 
 // Source line of length L with data at positions [y0, y0 + ny): row[y - y0];
 // zero elsewhere and when !ok.  Addresses are clamped into the row, so the
@@ -136,7 +140,7 @@ struct YzKArgs {
 // the first stage skips the zero half; 2: they fill it exactly (ys0 = 0,
 // nys = L/2), so the loads need no bounds either.
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
+__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
 {
@@ -156,7 +160,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 }
 
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
     BlockPos bp;
     const YzKArgs<R> a = batch_args(tab, starts, n, bp);
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 // nyt = L/2): the upper half of the inverse transform is never formed.
 // jf: J formed first by the first wave of block (0, 0) (see JFinal).
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
+__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *C, const cplx<R> *table, JFinal jf)
 {
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 }
 
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
     BlockPos bp;
     const YzKArgs<R> a = batch_args(tab, starts, n, bp);
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R
 constexpr bool gather_fits(int CO, int NC, int NR) { return NR * CO <= 4 && NR * NC <= 6; }
 constexpr size_t scatter_lds(int L, int CI, int NR, size_t csz)
 {
-    return ((size_t)TOF_YZ_ROWS * (kBlock / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
+    return ((size_t)TOF_YZ_ROWS * (yz_block(L) / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
 }
 constexpr bool scatter_fits(int L, int CI, int NC, int NR, size_t csz)
 {
@@ -294,7 +298,7 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH_B((k_yzsum_gather<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
-                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), st,
+                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(yz_block(L)), st,
                              gather_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                              a.rpg, a.yt0, a.nyt, kt, prod, a.part, table, a.part_kx_fast);
                 return hipGetLastError();
@@ -303,7 +307,7 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH_B((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
-                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), st,
+                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(yz_block(L)), st,
                              gather_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                              a.rpg, a.yt0, a.nyt, kt, prod, a.part, table, a.part_kx_fast);
                 return hipGetLastError();
@@ -315,7 +319,7 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
             TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>), grid, dim3(kBlock), st,
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>), grid, dim3(yz_block(L)), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -324,7 +328,7 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
             TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>), grid, dim3(kBlock), st,
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>), grid, dim3(yz_block(L)), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
