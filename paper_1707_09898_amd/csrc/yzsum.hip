@@ -51,11 +51,11 @@ using namespace tofdev;
 #endif
 
 constexpr int kE = 8;           // elements per thread of a y line
-// Threads per block: 256 for lines of 256 and 512 (8 or 4 lines side by
-// side), one wave for shorter lines (4 lines of 128, 8 of 64, 16 of 32):
+// Threads per block: 4 lines side by side for lines of 128 to 512 (256,
+// 128 or 64 threads), one wave for shorter ones (8 lines of 64, 16 of 32):
 // short lines come with few rows a block, and the gather's line slots are
 // added by one slot at the end.
-constexpr int yz_block(int L) { return L >= 256 ? 256 : 64; }
+constexpr int yz_block(int L) { return L >= 512 ? 256 : (L == 256 ? 128 : 64); }
 
 // Source line of length L with data at positions [y0, y0 + ny): row[y - y0];
 // zero elsewhere and when !ok.  Addresses are clamped into the row, so the
