@@ -20,7 +20,8 @@
 //           block sums (JFinal).
 //
 // A y line is held by P = L / E threads (thread p: positions p + P m, see
-// fft_reg.h); a 256-thread block runs NL = 256 / P lines side by side.
+// fft_reg.h); a block of yz_block(L) threads runs NL = yz_block(L) / P lines
+// side by side.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -199,10 +200,12 @@ __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(siz
 // the target box; line slot l handles rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys]; C is [CO][hx][nzt][nyt] with y from yt0 (the
 // input layout of the inverse x pass).
-// HALF: the target rows fill exactly the lower half of the line (yt0 = 0,
-// nyt = L/2): the upper half of the inverse transform is never formed.
+// HALF: 1: the target rows lie in the lower half of the line (yt0 + nyt <=
+// L/2, which the 2n padding always gives), 2: they fill it exactly (yt0 = 0,
+// nyt = L/2); either way the upper half of the inverse transform is never
+// formed, and with 2 the stores need no bounds.
 // jf: J formed first by the first wave of block (0, 0) (see JFinal).
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
 __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *C, const cplx<R> *table, JFinal jf)
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(siz
 #undef TOF_BGZ
 }
 
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
 __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
     BlockPos bp;
@@ -318,8 +321,8 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     if (a.nzs == 1) {
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>), grid, dim3(yz_block(L)), st,
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(yz_block(L)), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -327,8 +330,8 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     } else if (a.nzs <= NRM) {
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>), grid, dim3(yz_block(L)), st,
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(yz_block(L)), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -337,17 +340,16 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     return hipErrorInvalidValue;
 }
 
-// Where the many-row side lies in the y line: 2 when it fills exactly the
-// lower half (the source rows for the gather, the target rows for the
-// scatter), 1 when the gather's source rows lie in the lower half, else 0
-// (the scatter has forms 2 and 0 only).
+// Where the many-row side (the source rows for the gather, the target rows
+// for the scatter) lies in the y line: 2 when it fills exactly the lower
+// half, 1 when it lies in it, else 0.
 template <typename R, int L, int CI, int CO, int NC, int PAR>
 hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
                           const ProductDev &prod, const cplx<R> *table, bool check_only)
 {
     const bool gather = a.nzt <= kZsumMaxRows;
-    const int half = gather ? (a.ys0 == 0 && a.nys == L / 2 ? 2 : (a.ys0 + a.nys <= L / 2 ? 1 : 0))
-                            : (a.yt0 == 0 && a.nyt == L / 2 ? 2 : 0);
+    const int y0 = gather ? a.ys0 : a.yt0, ny = gather ? a.nys : a.nyt;
+    const int half = y0 == 0 && ny == L / 2 ? 2 : (y0 + ny <= L / 2 ? 1 : 0);
     if (half == 2) return launch_yzsum_h<R, L, CI, CO, NC, PAR, 2>(st, a, rows, kt, prod, table, check_only);
     if (half == 1) return launch_yzsum_h<R, L, CI, CO, NC, PAR, 1>(st, a, rows, kt, prod, table, check_only);
     return launch_yzsum_h<R, L, CI, CO, NC, PAR, 0>(st, a, rows, kt, prod, table, check_only);
