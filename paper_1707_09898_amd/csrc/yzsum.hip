@@ -20,8 +20,7 @@
 //           block sums (JFinal).
 //
 // A y line is held by P = L / E threads (thread p: positions p + P m, see
-// fft_reg.h); a block of yz_block(L) threads runs NL = yz_block(L) / P lines
-// side by side.
+// fft_reg.h); a 256-thread block runs NL = 256 / P lines side by side.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -52,11 +51,7 @@ using namespace tofdev;
 #endif
 
 constexpr int kE = 8;           // elements per thread of a y line
-// Threads per block: 4 lines side by side for lines of 128 to 512 (256,
-// 128 or 64 threads), one wave for shorter ones (8 lines of 64, 16 of 32):
-// short lines come with few rows a block, and the gather's line slots are
-// added by one slot at the end.
-constexpr int yz_block(int L) { return L >= 512 ? 256 : (L == 256 ? 128 : 64); }
+constexpr int kBlock = 256;     // threads per block
 
 // Source line of length L with data at positions [y0, y0 + ny): row[y - y0];
 // zero elsewhere and when !ok.  Addresses are clamped into the row, so the
@@ -141,7 +136,7 @@ struct YzKArgs {
 // the first stage skips the zero half; 2: they fill it exactly (ys0 = 0,
 // nys = L/2), so the loads need no bounds either.
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
-__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *part, const cplx<R> *table, int kxf)
 {
@@ -161,7 +156,7 @@ __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(siz
 }
 
 template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
-__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_GATHER_WAVES_F64 : TOF_YZ_GATHER_WAVES))) void k_yzsum_gather_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
     BlockPos bp;
     const YzKArgs<R> a = batch_args(tab, starts, n, bp);
@@ -200,13 +195,11 @@ __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(siz
 // the target box; line slot l handles rows l, l + NL, ... of that range.
 // A is [CI][hx][nzs][nys]; C is [CO][hx][nzt][nyt] with y from yt0 (the
 // input layout of the inverse x pass).
-// HALF: 1: the target rows lie in the lower half of the line (yt0 + nyt <=
-// L/2, which the 2n padding always gives), 2: they fill it exactly (yt0 = 0,
-// nyt = L/2); either way the upper half of the inverse transform is never
-// formed, and with 2 the stores need no bounds.
+// HALF: the target rows fill exactly the lower half of the line (yt0 = 0,
+// nyt = L/2): the upper half of the inverse transform is never formed.
 // jf: J formed first by the first wave of block (0, 0) (see JFinal).
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
-__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter(
     const cplx<R> *A, int hx, int ys0, int nys, int zs0, int nzs, int zt0, int nzt, int rpg, int yt0, int nyt,
     KtDev<R> kt, ProductDev prod, cplx<R> *C, const cplx<R> *table, JFinal jf)
 {
@@ -225,8 +218,8 @@ __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(siz
 #undef TOF_BGZ
 }
 
-template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, int HALF>
-__global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
+template <typename R, int L, int E, int CI, int CO, int NC, int NR, int PAR, bool HALF>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? TOF_YZ_SCATTER_WAVES_F64 : TOF_YZ_SCATTER_WAVES))) void k_yzsum_scatter_batch(const YzKArgs<R> *__restrict__ tab, const int *__restrict__ starts, int n)
 {
     BlockPos bp;
     const YzKArgs<R> a = batch_args(tab, starts, n, bp);
@@ -267,7 +260,7 @@ __global__ __launch_bounds__(yz_block(L)) __attribute__((amdgpu_waves_per_eu(siz
 constexpr bool gather_fits(int CO, int NC, int NR) { return NR * CO <= 4 && NR * NC <= 6; }
 constexpr size_t scatter_lds(int L, int CI, int NR, size_t csz)
 {
-    return ((size_t)TOF_YZ_ROWS * (yz_block(L) / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
+    return ((size_t)TOF_YZ_ROWS * (kBlock / (L / kE)) * regfft::padded_len(L) + (size_t)NR * CI * L) * csz;
 }
 constexpr bool scatter_fits(int L, int CI, int NC, int NR, size_t csz)
 {
@@ -301,7 +294,7 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, 1)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH_B((k_yzsum_gather<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
-                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(yz_block(L)), st,
+                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(kBlock), st,
                              gather_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                              a.rpg, a.yt0, a.nyt, kt, prod, a.part, table, a.part_kx_fast);
                 return hipGetLastError();
@@ -310,7 +303,7 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
             if constexpr (gather_fits(CO, NC, NRM)) {
                 if (check_only) return hipSuccess;
                 TOF_LAUNCH_B((k_yzsum_gather<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
-                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(yz_block(L)), st,
+                             (k_yzsum_gather_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(kBlock), st,
                              gather_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                              a.rpg, a.yt0, a.nyt, kt, prod, a.part, table, a.part_kx_fast);
                 return hipGetLastError();
@@ -321,8 +314,8 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     if (a.nzs == 1) {
         if constexpr (scatter_fits(L, CI, NC, 1, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF>), grid, dim3(yz_block(L)), st,
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, 1, PAR, HALF == 2>), grid, dim3(kBlock), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -330,8 +323,8 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     } else if (a.nzs <= NRM) {
         if constexpr (scatter_fits(L, CI, NC, NRM, csz)) {
             if (check_only) return hipSuccess;
-            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF>),
-                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF>), grid, dim3(yz_block(L)), st,
+            TOF_LAUNCH_B((k_yzsum_scatter<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>),
+                         (k_yzsum_scatter_batch<R, L, kE, CI, CO, NC, NRM, PAR, HALF == 2>), grid, dim3(kBlock), st,
                          scatter_args(a, kt, prod, table), a.A, a.hx, a.ys0, a.nys, a.zs0, a.nzs, a.zt0, a.nzt,
                          a.rpg, a.yt0, a.nyt, kt, prod, a.C, table, a.jf);
             return hipGetLastError();
@@ -340,16 +333,17 @@ hipError_t launch_yzsum_h(hipStream_t st, const YzSumArgs<R> &a, int rows, const
     return hipErrorInvalidValue;
 }
 
-// Where the many-row side (the source rows for the gather, the target rows
-// for the scatter) lies in the y line: 2 when it fills exactly the lower
-// half, 1 when it lies in it, else 0.
+// Where the many-row side lies in the y line: 2 when it fills exactly the
+// lower half (the source rows for the gather, the target rows for the
+// scatter), 1 when the gather's source rows lie in the lower half, else 0
+// (the scatter has forms 2 and 0 only).
 template <typename R, int L, int CI, int CO, int NC, int PAR>
 hipError_t launch_yzsum_l(hipStream_t st, const YzSumArgs<R> &a, int rows, const KtDev<R> &kt,
                           const ProductDev &prod, const cplx<R> *table, bool check_only)
 {
     const bool gather = a.nzt <= kZsumMaxRows;
-    const int y0 = gather ? a.ys0 : a.yt0, ny = gather ? a.nys : a.nyt;
-    const int half = y0 == 0 && ny == L / 2 ? 2 : (y0 + ny <= L / 2 ? 1 : 0);
+    const int half = gather ? (a.ys0 == 0 && a.nys == L / 2 ? 2 : (a.ys0 + a.nys <= L / 2 ? 1 : 0))
+                            : (a.yt0 == 0 && a.nyt == L / 2 ? 2 : 0);
     if (half == 2) return launch_yzsum_h<R, L, CI, CO, NC, PAR, 2>(st, a, rows, kt, prod, table, check_only);
     if (half == 1) return launch_yzsum_h<R, L, CI, CO, NC, PAR, 1>(st, a, rows, kt, prod, table, check_only);
     return launch_yzsum_h<R, L, CI, CO, NC, PAR, 0>(st, a, rows, kt, prod, table, check_only);

@@ -197,7 +197,7 @@ GRAD_CASES = [
     ("lower_half_offset_design", lambda: dataclasses.replace(
         wl.small_random(47, n=(13, 11, 10), design=(2, 12, 3, 10, 0, 6)), pad=(32, 32, 20))),
     # the same with varying M0 and a vector target: three components through
-    # the lower-half forms of the x pass, the gather and the scatter
+    # the lower-half forms of the x pass and the gather
     ("lower_half_vector", lambda: dataclasses.replace(
         wl.small_random(48, n=(13, 11, 10), j_kind=wl.J_MEAN_SQ_H_TARGET, varying_m0=True), pad=(32, 32, 20))),
 ]
