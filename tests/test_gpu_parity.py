@@ -588,3 +588,20 @@ def test_gpu_profile_launch_times_add_up_to_the_step(torch):
     btotal = sum(burst[i] for (i, _, _, _) in used)
     assert 0.9 * step <= btotal <= 1.15 * step, (btotal, step)
     e.close()
+
+
+def test_gpu_profile_burst_rejects_bad_arguments(torch):
+    """tof_profile_burst: refused with timing off, repeats outside [1, 4096]
+    and a mask naming no slot; tof_profile_burst_read refuses a null array."""
+    t = tof()
+    L = t.lib()
+    e = t.Engine((8, 8, 8), (1.0, 1.0, 1.0), "f32")
+    assert L.tof_profile_burst(e._ctx, 1, 10) == -1          # timing off
+    e.profile(True)
+    assert L.tof_profile_burst(e._ctx, 1, 0) == -1
+    assert L.tof_profile_burst(e._ctx, 1, 4097) == -1
+    assert L.tof_profile_burst(e._ctx, 1 << 12, 10) == -1    # TOF_PROFILE_SLOTS = 12
+    assert L.tof_profile_burst(e._ctx, 1, 4096) == 0
+    assert L.tof_profile_burst_read(e._ctx, None) == -1
+    e.profile(False)
+    e.close()
