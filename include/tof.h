@@ -386,10 +386,9 @@ const char *tof_last_error(const tof_ctx *ctx);
  * The contexts and buffers are borrowed: they must stay valid, and their
  * design, objective and options unchanged, while the batch is used.
  * tof_batch_run enqueues one evaluation of every design on `stream` (no
- * allocation, no synchronization: capturable into a graph): the launches of
- * a pass run side by side on up to four streams the batch owns (default
- * priority), forked from and joined back to `stream` with events; results
- * are those of tof_objective_and_grad on each context (the same kernels).
+ * allocation, no synchronization: capturable into a graph), its launches
+ * one after another on `stream`; results are those of
+ * tof_objective_and_grad on each context (the same kernels).
  * Runs of one batch must not overlap.
  * Requires the fused passes (TOF_OPT_ZSUM, TOF_OPT_FUSE_YZ and
  * TOF_OPT_FUSE_OBJECTIVE on, power-of-two Lx and Ly from 32 to 512, an

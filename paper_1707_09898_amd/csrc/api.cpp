@@ -129,26 +129,15 @@ struct tof_batch {
     };
     std::vector<std::vector<Group>> passes;
     void *buf = nullptr;   // one device allocation holding every table
-    // the groups of a pass run side by side on these streams (default
-    // priority), joined to the caller's stream between passes
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> events;   // [0]: the caller's stream; [1 + i]: stream i
     std::string err;
 };
 
-constexpr int kBatchStreams = 4;
-// Side streams are off: forking a pass's groups onto them and joining back
-// with events measured slower than running the groups one after another
-// (each join left 30-40 us with no kernel running).
-constexpr int kBatchSideStreams = 0;
-
+// The groups of a pass run one after another on the caller's stream:
+// forking them onto side streams and joining back with events measured
+// slower (each join left 30-40 us with no kernel running).
 void batch_release(tof_batch *b)
 {
-    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
-    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
     if (b->buf) (void)hipFree(b->buf);
-    b->events.clear();
-    b->streams.clear();
     b->buf = nullptr;
 }
 
@@ -1432,24 +1421,6 @@ tof_status tof_batch_create(tof_ctx *const *ctxs, const void *const *rho, double
             b->passes[k][q].tab = (unsigned char *)b->buf + pend[k][q].tab_off;
             b->passes[k][q].starts = (int *)((unsigned char *)b->buf + pend[k][q].starts_off);
         }
-    size_t widest = 0;
-    for (const auto &pass : b->passes) widest = std::max(widest, pass.size());
-    const int ns = (int)std::min<size_t>(kBatchStreams, widest > 1 ? widest : 0) * kBatchSideStreams;
-    for (int i = 0; i < ns && e == hipSuccess; ++i) {
-        hipStream_t sti = nullptr;
-        e = hipStreamCreateWithFlags(&sti, hipStreamNonBlocking);
-        if (e == hipSuccess) b->streams.push_back(sti);
-    }
-    for (int i = 0; i < (ns ? ns + 1 : 0) && e == hipSuccess; ++i) {
-        hipEvent_t ev = nullptr;
-        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess) b->events.push_back(ev);
-    }
-    if (e != hipSuccess) {
-        batch_release(b);
-        delete b;
-        return hip_fail(nullptr, e, "tof_batch_create (streams)");
-    }
     *out = b;
     return TOF_OK;
 }
@@ -1458,40 +1429,18 @@ tof_status tof_batch_run(tof_batch *b, void *stream)
 {
     if (!b) return fail(nullptr, TOF_ERR_INVALID, "null batch");
     hipStream_t st = (hipStream_t)stream;
-    auto check = [&](hipError_t e, const char *what) {
-        if (e == hipSuccess) return TOF_OK;
-        b->err = std::string(what) + ": " + hipGetErrorString(e);
-        return fail(nullptr, TOF_ERR_HIP, b->err);
-    };
-    tof_status s;
     for (const auto &pass : b->passes) {
-        // one group: on the caller's stream; several: side by side on the
-        // batch's streams, which start after everything before on the
-        // caller's stream and which the caller's stream then waits for
-        const bool fork = pass.size() > 1 && !b->streams.empty();
-        const int ns = fork ? (int)std::min(pass.size(), b->streams.size()) : 0;
-        if (fork) {
-            if ((s = check(hipEventRecord(b->events[0], st), "hipEventRecord")) != TOF_OK) return s;
-            for (int i = 0; i < ns; ++i)
-                if ((s = check(hipStreamWaitEvent(b->streams[i], b->events[0], 0), "hipStreamWaitEvent")) != TOF_OK)
-                    return s;
-        }
-        for (size_t q = 0; q < pass.size(); ++q) {
-            const tof_batch::Group &g = pass[q];
+        for (const tof_batch::Group &g : pass) {
             const void *tab = g.tab;
             const int *starts = g.starts;
             int n = g.n;
             void *args[] = {(void *)&tab, (void *)&starts, (void *)&n};
-            hipStream_t sq = fork ? b->streams[q % ns] : st;
-            if ((s = check(hipLaunchKernel(g.kernel, dim3((unsigned)g.blocks), g.block, args, 0, sq),
-                           "hipLaunchKernel")) != TOF_OK)
-                return s;
-        }
-        if (fork)
-            for (int i = 0; i < ns; ++i) {
-                if ((s = check(hipEventRecord(b->events[1 + i], b->streams[i]), "hipEventRecord")) != TOF_OK) return s;
-                if ((s = check(hipStreamWaitEvent(st, b->events[1 + i], 0), "hipStreamWaitEvent")) != TOF_OK) return s;
+            const hipError_t e = hipLaunchKernel(g.kernel, dim3((unsigned)g.blocks), g.block, args, 0, st);
+            if (e != hipSuccess) {
+                b->err = std::string("hipLaunchKernel: ") + hipGetErrorString(e);
+                return fail(nullptr, TOF_ERR_HIP, b->err);
             }
+        }
     }
     return TOF_OK;
 }
